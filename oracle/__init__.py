@@ -1,0 +1,133 @@
+"""Sequential CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never links, loads
+or calls it, and it shares no code with the GPU path (the two only share the
+seeded input generators in ``graphgen``).
+
+Functions (plain definitions, see ``oracle.c`` for the citations):
+
+* :func:`scc_labels`  -- Tarjan's SCC, canonical label = min vertex id per SCC;
+* :func:`reach_pairs` -- per-source BFS reach restricted to label-equal arcs;
+* :func:`check_partition` -- certificate (mutual reachability inside every
+  class, acyclic class graph, label = class minimum);
+* :func:`hashbag_model` -- the hash bag's ExtractAll contract (Section 3.3):
+  the extracted multiset equals the multiset inserted since the last extract;
+* :func:`policy_forward` -- float32 forward pass of the round-policy MLP.
+
+The C part is compiled with gcc (``build``); the MLP forward is numpy.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        lib.or_tarjan.argtypes = [i64, vp, vp, vp]
+        lib.or_reach_pairs.argtypes = [i64, vp, vp, vp, i64, vp, vp, i64, ctypes.POINTER(i64)]
+        lib.or_check_partition.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.POINTER(i64)]
+        _lib = lib
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def scc_labels(n: int, off, adj) -> np.ndarray:
+    """labels[v] = minimum vertex id of v's strongly connected component."""
+    off, adj = _i32(off), _i32(adj)
+    out = np.empty(max(n, 1), np.int32)
+    rc = _load().or_tarjan(n, off.ctypes.data, adj.ctypes.data if len(adj) else None, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("or_tarjan failed: %d" % rc)
+    return out[:n]
+
+
+def scc_graph(g) -> np.ndarray:
+    return scc_labels(g.n, g.out_off, g.out_adj)
+
+
+def reach_pairs(n: int, off, adj, labels, sources) -> np.ndarray:
+    """Sorted (vertex, source_index) pairs, shape (count, 2), of the
+    label-restricted reach from each source (arcs (u,w) need labels[u]==labels[w]>=0)."""
+    off, adj, labels, sources = _i32(off), _i32(adj), _i32(labels), _i32(sources)
+    lib = _load()
+    cnt = ctypes.c_int64(0)
+    cap = max(16, 4 * len(sources))
+    while True:
+        pairs = np.empty(2 * cap, np.int32)
+        rc = lib.or_reach_pairs(n, off.ctypes.data, adj.ctypes.data if len(adj) else None, labels.ctypes.data,
+                                len(sources), sources.ctypes.data if len(sources) else None, pairs.ctypes.data,
+                                cap, ctypes.byref(cnt))
+        if rc == -3:
+            cap = int(cnt.value)
+            continue
+        if rc != 0:
+            raise ValueError("or_reach_pairs rejected its input: %d" % rc)
+        return pairs[: 2 * cnt.value].reshape(-1, 2)
+
+
+def check_partition(g, labels):
+    """(code, vertex): code 0 = labels are the canonical SCC partition."""
+    labels = _i32(labels)
+    bad = ctypes.c_int64(-1)
+    rc = _load().or_check_partition(g.n, _i32(g.out_off).ctypes.data, _i32(g.out_adj).ctypes.data,
+                                    _i32(g.in_off).ctypes.data, _i32(g.in_adj).ctypes.data, labels.ctypes.data,
+                                    ctypes.byref(bad))
+    return int(rc), int(bad.value)
+
+
+def hashbag_model(inserted_batches):
+    """ExtractAll contract (Section 3.3): after any sequence of concurrent
+    Inserts, ExtractAll returns exactly the inserted multiset (no dedupe).
+    Returns the expected extract, sorted, for each batch."""
+    return [np.sort(np.asarray(b, dtype=np.int64)) for b in inserted_batches]
+
+
+def policy_forward(weights: np.ndarray, feats: np.ndarray, n_in: int = 5, hidden: int = 32, n_out: int = 8):
+    """Float32 forward of the 3-layer MLP (n_in -> hidden -> hidden -> n_out),
+    ReLU between layers.  ``weights`` is the flat blob
+    [W1 (hidden x n_in), b1, W2 (hidden x hidden), b2, W3 (n_out x hidden), b3]."""
+    w = np.asarray(weights, dtype=np.float32)
+    x = np.asarray(feats, dtype=np.float32)
+    o = 0
+
+    def take(r, c):
+        nonlocal o
+        a = w[o:o + r * c].reshape(r, c)
+        o += r * c
+        return a
+
+    W1 = take(hidden, n_in)
+    b1 = take(1, hidden)[0]
+    W2 = take(hidden, hidden)
+    b2 = take(1, hidden)[0]
+    W3 = take(n_out, hidden)
+    b3 = take(1, n_out)[0]
+    h = np.maximum(x @ W1.T + b1, np.float32(0))
+    h = np.maximum(h @ W2.T + b2, np.float32(0))
+    return (h @ W3.T + b3).astype(np.float32)

@@ -1,0 +1,248 @@
+/*
+ * Sequential CPU oracle for strongly connected components and reachability.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * loads this file; only the tests, the smoke check and the CPU baseline of the
+ * benchmark do.  It shares no code with the GPU path.
+ *
+ * What it computes, each by its plain definition:
+ *   or_tarjan          SCC partition of a digraph (the SCC definition of
+ *                      Section 2, computed by Tarjan's sequential algorithm,
+ *                      which the paper uses as its exact baseline "SEQ",
+ *                      Section 6), written out as the canonical label
+ *                      "minimum vertex id of the vertex's SCC".
+ *   or_reach_pairs     the reachability pairs {(v, j) : s_j ~> v} of a source
+ *                      set (Section 2, "Reachability Search"), restricted, as
+ *                      the multi-reachability search of Algorithm 1 is, to
+ *                      arcs (u, w) whose endpoints carry the same label; here
+ *                      labels < 0 mark excluded vertices.  One plain BFS per
+ *                      source.
+ *   or_check_partition an implementation-free certificate that a labelling is
+ *                      the SCC partition: (i) inside every class, the minimum
+ *                      member reaches and is reached by every member using
+ *                      only arcs inside the class; (ii) the graph of classes
+ *                      is acyclic; (iii) every label is the minimum id of its
+ *                      class.  (i) says classes are strongly connected,
+ *                      (ii) that no two classes can merge, so together they
+ *                      characterise the SCCs.
+ *
+ * Error codes: 0 ok; -1 invalid argument; -2 out of memory; -3 capacity
+ * exceeded (or_reach_pairs: *count still holds the full size).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Tarjan's algorithm, iterative: an explicit frame stack of (vertex, next arc)
+ * replaces the recursion so that graphs with 1e8 vertices do not overflow the
+ * call stack. labels[v] <- min id of v's SCC. */
+int or_tarjan(int64_t n, const int32_t *off, const int32_t *adj, int32_t *labels) {
+    if (n < 0) return -1;
+    if (n == 0) return 0;
+    int32_t *index = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *low = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t *onstack = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *sstack = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *fv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *fpos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!index || !low || !onstack || !sstack || !fv || !fpos) {
+        free(index); free(low); free(onstack); free(sstack); free(fv); free(fpos);
+        return -2;
+    }
+    for (int64_t v = 0; v < n; v++) index[v] = -1;
+    int32_t counter = 0;
+    int64_t sp = 0; /* SCC stack size */
+    for (int64_t root = 0; root < n; root++) {
+        if (index[root] != -1) continue;
+        int64_t fp = 0; /* frame stack size */
+        fv[0] = (int32_t)root;
+        fpos[0] = off[root];
+        index[root] = low[root] = counter++;
+        sstack[sp++] = (int32_t)root;
+        onstack[root] = 1;
+        fp = 1;
+        while (fp > 0) {
+            int32_t v = fv[fp - 1];
+            if (fpos[fp - 1] < off[v + 1]) {
+                int32_t w = adj[fpos[fp - 1]++];
+                if (index[w] == -1) {
+                    index[w] = low[w] = counter++;
+                    sstack[sp++] = w;
+                    onstack[w] = 1;
+                    fv[fp] = w;
+                    fpos[fp] = off[w];
+                    fp++;
+                } else if (onstack[w] && index[w] < low[v]) {
+                    low[v] = index[w];
+                }
+            } else {
+                fp--;
+                if (low[v] == index[v]) {
+                    /* v roots an SCC: the members are on top of the stack */
+                    int64_t top = sp;
+                    int32_t mn = v;
+                    do {
+                        sp--;
+                        if (sstack[sp] < mn) mn = sstack[sp];
+                    } while (sstack[sp] != v);
+                    for (int64_t i = sp; i < top; i++) {
+                        labels[sstack[i]] = mn;
+                        onstack[sstack[i]] = 0;
+                    }
+                }
+                if (fp > 0) {
+                    int32_t p = fv[fp - 1];
+                    if (low[v] < low[p]) low[p] = low[v];
+                }
+            }
+        }
+    }
+    free(index); free(low); free(onstack); free(sstack); free(fv); free(fpos);
+    return 0;
+}
+
+/* One BFS per source over arcs (u, w) with labels[u] == labels[w] >= 0.
+ * Output pairs (vertex, source index) sorted by (source index, vertex) into
+ * pairs[2*i], pairs[2*i+1]; *count receives the total even when it exceeds
+ * cap (then -3 is returned and only the first cap pairs are written).
+ * Sources must be distinct, in range and not excluded (labels >= 0). */
+int or_reach_pairs(int64_t n, const int32_t *off, const int32_t *adj, const int32_t *labels, int64_t k,
+                   const int32_t *sources, int32_t *pairs, int64_t cap, int64_t *count) {
+    if (n < 0 || k < 0 || (k > 0 && !sources) || !count) return -1;
+    *count = 0;
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t *mark = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!seen || !queue || !mark) { free(seen); free(queue); free(mark); return -2; }
+    for (int64_t j = 0; j < k; j++) {
+        int32_t s = sources[j];
+        if (s < 0 || s >= n || labels[s] < 0 || mark[s]) { free(seen); free(queue); free(mark); return -1; }
+        mark[s] = 1;
+    }
+    for (int64_t v = 0; v < n; v++) seen[v] = -1;
+    int64_t total = 0;
+    for (int64_t j = 0; j < k; j++) {
+        int32_t s = sources[j];
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        seen[s] = (int32_t)j;
+        while (head < tail) {
+            int32_t u = queue[head++];
+            for (int64_t e = off[u]; e < off[u + 1]; e++) {
+                int32_t w = adj[e];
+                if (labels[w] != labels[u] || seen[w] == (int32_t)j) continue;
+                seen[w] = (int32_t)j;
+                queue[tail++] = w;
+            }
+        }
+        /* the visited set, ascending by vertex */
+        qsort(queue, (size_t)tail, sizeof(int32_t), cmp_i32);
+        for (int64_t a = 0; a < tail; a++) {
+            if (total < cap) {
+                pairs[2 * total] = queue[a];
+                pairs[2 * total + 1] = (int32_t)j;
+            }
+            total++;
+        }
+    }
+    free(seen); free(queue); free(mark);
+    *count = total;
+    return total > cap ? -3 : 0;
+}
+
+/* Certificate check.  Returns 0 when labels is the canonical SCC labelling,
+ * 1 if a class is not strongly connected through its own arcs, 2 if the class
+ * graph has a cycle, 3 if a label is not the minimum id of its class (or out
+ * of range).  *bad receives an offending vertex (or -1). */
+int or_check_partition(int64_t n, const int32_t *out_off, const int32_t *out_adj, const int32_t *in_off,
+                       const int32_t *in_adj, const int32_t *labels, int64_t *bad) {
+    *bad = -1;
+    if (n < 0) return -1;
+    if (n == 0) return 0;
+    /* (iii) labels are the minimum member: label in range, label <= v and
+     * the representative labels itself */
+    for (int64_t v = 0; v < n; v++) {
+        int32_t l = labels[v];
+        if (l < 0 || l >= n || l > v || labels[l] != l) { *bad = v; return 3; }
+    }
+    /* group members by class */
+    int64_t *start = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int32_t *memb = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!start || !memb || !seen || !queue) { free(start); free(memb); free(seen); free(queue); return -2; }
+    for (int64_t v = 0; v < n; v++) start[labels[v] + 1]++;
+    for (int64_t c = 0; c < n; c++) start[c + 1] += start[c];
+    {
+        int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        memcpy(cur, start, sizeof(int64_t) * (size_t)n);
+        for (int64_t v = 0; v < n; v++) memb[cur[labels[v]]++] = (int32_t)v;
+        free(cur);
+    }
+    /* (i) mutual reachability inside each class, both directions */
+    for (int dir = 0; dir < 2; dir++) {
+        const int32_t *off = dir ? in_off : out_off;
+        const int32_t *adj = dir ? in_adj : out_adj;
+        for (int64_t v = 0; v < n; v++) seen[v] = -1;
+        for (int64_t c = 0; c < n; c++) {
+            int64_t size = start[c + 1] - start[c];
+            if (size == 0) continue;
+            int64_t head = 0, tail = 0;
+            queue[tail++] = (int32_t)c;
+            seen[c] = (int32_t)c;
+            while (head < tail) {
+                int32_t u = queue[head++];
+                for (int64_t e = off[u]; e < off[u + 1]; e++) {
+                    int32_t w = adj[e];
+                    if (labels[w] != (int32_t)c || seen[w] == (int32_t)c) continue;
+                    seen[w] = (int32_t)c;
+                    queue[tail++] = w;
+                }
+            }
+            if (tail != size) {
+                for (int64_t i = start[c]; i < start[c + 1]; i++)
+                    if (seen[memb[i]] != (int32_t)c) { *bad = memb[i]; break; }
+                free(start); free(memb); free(seen); free(queue);
+                return 1;
+            }
+        }
+    }
+    /* (ii) Kahn's topological sort of the class graph (parallel arcs are
+     * counted with multiplicity, which Kahn's algorithm tolerates) */
+    int64_t *indeg = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    int64_t nclass = 0;
+    for (int64_t c = 0; c < n; c++) nclass += (start[c + 1] > start[c]);
+    for (int64_t u = 0; u < n; u++)
+        for (int64_t e = out_off[u]; e < out_off[u + 1]; e++) {
+            int32_t w = out_adj[e];
+            if (labels[w] != labels[u]) indeg[labels[w]]++;
+        }
+    int64_t head = 0, tail = 0, done = 0;
+    for (int64_t c = 0; c < n; c++)
+        if (start[c + 1] > start[c] && indeg[c] == 0) queue[tail++] = (int32_t)c;
+    while (head < tail) {
+        int32_t c = queue[head++];
+        done++;
+        for (int64_t i = start[c]; i < start[c + 1]; i++) {
+            int32_t u = memb[i];
+            for (int64_t e = out_off[u]; e < out_off[u + 1]; e++) {
+                int32_t w = out_adj[e];
+                int32_t d = labels[w];
+                if (d != c && --indeg[d] == 0) queue[tail++] = d;
+            }
+        }
+    }
+    int rc = 0;
+    if (done != nclass) {
+        for (int64_t c = 0; c < n; c++)
+            if (indeg[c] > 0) { *bad = c; break; }
+        rc = 2;
+    }
+    free(indeg); free(start); free(memb); free(seen); free(queue);
+    return rc;
+}
