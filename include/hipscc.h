@@ -1,0 +1,204 @@
+/*
+ * hipscc -- strongly connected components on one MI355X (gfx950) by the
+ * BGSS randomized algorithm with vertical granularity control (VGC) and a
+ * parallel hash-bag frontier.
+ *
+ * Paper: Wang, Dong, Gu, Sun, "Parallel Strong Connectivity Based on Faster
+ * Reachability", SIGMOD 2023 (arXiv 2303.04934).
+ *
+ * C ABI.  Plain integers and pointers only.  Every pointer documented as
+ * "device" must point to memory of the device the context was created on;
+ * the caller owns it and the library never frees it.  "host" pointers are
+ * ordinary CPU memory.  Calls are synchronous: they enqueue work on the
+ * context's stream and wait for it before returning, so outputs are ready on
+ * return.  Inputs are never modified.  A context is not thread safe; use one
+ * per host thread.  No C++ exception crosses this interface.
+ *
+ * Errors: every call returns an scc_status; on failure scc_last_error(ctx)
+ * returns a message that stays valid until the next call on that context.
+ */
+#ifndef HIPSCC_H
+#define HIPSCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t scc_status;
+enum {
+    SCC_OK = 0,
+    SCC_EINVAL = -1,     /* bad argument (null pointer, bad size, bad option) */
+    SCC_EGRAPH = -2,     /* the CSR failed validation */
+    SCC_ENOMEM = -3,     /* device allocation failed */
+    SCC_ECAPACITY = -4,  /* caller-provided output buffer too small */
+    SCC_EHIP = -5,       /* a HIP runtime call failed */
+    SCC_EPOLICY = -6,    /* malformed policy weights */
+    SCC_EINTERNAL = -7   /* an internal invariant failed (a bug) */
+};
+
+typedef struct scc_ctx scc_ctx_t;
+
+/* A directed graph G = (V, E), |V| = n, |E| = m (Section 2, notation), as a
+ * CSR of out-arcs and the CSR of the transpose graph G^T (the backward search
+ * runs on G^T, Section 2, "Reachability Search").  All four arrays are device
+ * int32:
+ *   out_off[n+1]: out_off[0] = 0, nondecreasing, out_off[n] = m;
+ *   out_adj[m]:   targets in [0, n);
+ *   in_off/in_adj: the same arc multiset, grouped by target.
+ * 0 <= n < 2^31 and 0 <= m < 2^31.  Self loops and parallel arcs are allowed
+ * (neither changes the SCCs). */
+typedef struct {
+    int32_t n;
+    int32_t m;
+    const int32_t *out_off;
+    const int32_t *out_adj;
+    const int32_t *in_off;
+    const int32_t *in_adj;
+} scc_graph_t;
+
+/* Tunables.  Fill with scc_default_options() and change fields; passing NULL
+ * means the defaults.  None of them changes a result, only work and rounds.
+ *   tau          VGC budget: arcs a local search examines before it stops and
+ *                hands its queue to the next frontier (Section 3.2; default
+ *                512).  tau <= 1 disables local search (plain frontier BFS,
+ *                Algorithm 2).
+ *   beta         prefix-doubling multiplier for the source batches
+ *                (Algorithm 1; Table 1 uses 1.5).  Must be > 1.
+ *   lambda_log2  log2 of the hash bag's first chunk (Table 1: 10).
+ *   sigma        samples that trigger a hash bag chunk advance (Table 1: 50).
+ *   kappa        stripe probes before an insert forces a chunk advance.
+ *   alpha        target load factor of a bag chunk (0 < alpha < 1).
+ *   seed         seed of the random vertex permutation.
+ *   policy       0 = fixed schedule, 1 = learned per-round policy (needs
+ *                scc_policy_load; falls back to the fixed schedule otherwise).
+ *   dense        single-source search direction mode: -1 automatic,
+ *                0 never pull, 1 always pull (Section 4.2).
+ *   validate     1 = check the CSR (O(n + m)) before running.
+ *   trim         1 = remove vertices of zero in- or out-degree first (4.1).
+ *   table_init   reach table slots for the first multi-source batch (power of
+ *                two); 0 = the sizing heuristic of Section 4.5.
+ *   seeds_per_wave frontier entries a wavefront takes per fetch (1..64);
+ *                0 = chosen from the frontier size. */
+typedef struct {
+    int32_t tau;
+    float beta;
+    int32_t lambda_log2;
+    int32_t sigma;
+    int32_t kappa;
+    float alpha;
+    uint64_t seed;
+    int32_t policy;
+    int32_t dense;
+    int32_t validate;
+    int32_t trim;
+    int64_t table_init;
+    int32_t seeds_per_wave;
+    int32_t reserved[7];
+} scc_options_t;
+
+/* Per-call statistics (host struct, written when non-NULL).  Times are
+ * milliseconds measured with HIP events on the context's stream.  The five
+ * phases follow the paper's breakdown (Section 4 / Figure 8): trimming,
+ * first SCC (single-source searches), multi-search, hash table resizing and
+ * labeling (relabel + canonicalisation). */
+typedef struct {
+    double ms_total, ms_trim, ms_first, ms_multi, ms_resize, ms_label;
+    int64_t n, m;
+    int64_t batches;          /* source batches that ran a search */
+    int64_t rounds_first;     /* frontier rounds of the single-source search (both directions) */
+    int64_t rounds_multi;     /* frontier rounds of all multi-source searches */
+    int64_t dense_rounds;     /* rounds that ran in pull mode */
+    int64_t entries_expanded; /* frontier / local-queue entries expanded */
+    int64_t arcs_scanned;     /* adjacency slots read by searches */
+    int64_t claim_attempts;   /* label-equal targets that were tried */
+    int64_t claims;           /* successful claims = reachability pairs found */
+    int64_t bag_inserts;      /* hash bag inserts */
+    int64_t bag_chunk_advances;
+    int64_t table_restarts;   /* searches re-run with a larger table */
+    int64_t trimmed;          /* vertices finished by trimming */
+    int64_t n_scc;            /* number of SCCs (scc_labels only) */
+    int64_t policy_calls;     /* rounds decided by the learned policy */
+    int64_t policy_fallbacks; /* rounds where the policy output was unusable */
+    int64_t bytes_alg;        /* algorithmic HBM bytes (see DESIGN) */
+    int64_t reserved[8];
+} scc_stats_t;
+
+/* Library version string (static storage). */
+const char *scc_version(void);
+
+/* Default options (the paper's Table 1 values where it gives one). */
+scc_status scc_default_options(scc_options_t *opt);
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t to run
+ * on (NULL: the context creates and owns one).  The context owns all scratch
+ * memory; it grows on demand and is freed by scc_destroy. */
+scc_status scc_create(scc_ctx_t **ctx, int device, void *stream);
+void scc_destroy(scc_ctx_t *ctx);
+const char *scc_last_error(const scc_ctx_t *ctx);
+
+/* SCC labels (Algorithm 1 with Section 4's implementation details).
+ * labels_out: device int32[n]; on return labels_out[v] is the minimum vertex
+ * id of v's strongly connected component (the output of Section 2's problem
+ * statement, made canonical).  Stats may be NULL. */
+scc_status scc_labels(scc_ctx_t *ctx, const scc_graph_t *g, int32_t *labels_out, const scc_options_t *opt,
+                      scc_stats_t *stats);
+
+/* Reachability pairs (Section 2, "Reachability Search"; the MultiReach of
+ * Algorithm 1).  dir = 0 searches G (out_*), dir = 1 searches G^T (in_*).
+ * sources: device int32[k], distinct, with labels[s] >= 0.  labels: device
+ * int32[n]; an arc (u, w) is used only if labels[u] == labels[w] (Algorithm 1
+ * skips arcs whose endpoints have different labels); vertices with a negative
+ * label are excluded.  Output: every pair (v, j) with sources[j] ~> v,
+ * including (sources[j], j), exactly once, in unspecified order, written as
+ * pairs_out[2*i] = v, pairs_out[2*i+1] = j (device int32[2 * capacity]).
+ * *n_pairs (host) always receives the number of pairs; if it exceeds
+ * capacity the call returns SCC_ECAPACITY and pairs_out is unspecified.
+ * With k == 1 the single-source (visited-flag) search is used. */
+scc_status scc_reach(scc_ctx_t *ctx, const scc_graph_t *g, int32_t dir, const int32_t *sources, int32_t k,
+                     const int32_t *labels, int32_t *pairs_out, int64_t capacity, int64_t *n_pairs,
+                     const scc_options_t *opt, scc_stats_t *stats);
+
+/* SCC labels of G independent graphs in one pass (their disjoint union is
+ * searched by the same kernels).  vtx_base and arc_base are host int64[G+1]
+ * prefix sums of the graphs' vertex and arc counts.  Device arrays, graph g's
+ * part stored contiguously:
+ *   out_off/in_off: int32[vtx_base[G] + G]; graph g's n_g + 1 LOCAL offsets
+ *                   start at index vtx_base[g] + g;
+ *   out_adj/in_adj: int32[arc_base[G]]; graph g's arcs start at arc_base[g]
+ *                   and hold LOCAL vertex ids in [0, n_g).
+ * labels_out: device int32[vtx_base[G]]; graph g's labels start at
+ * vtx_base[g] and are LOCAL ids (min local id of the SCC).  The total vertex
+ * count must stay below 2^31; the total arc count may exceed it. */
+scc_status scc_labels_batched(scc_ctx_t *ctx, int32_t G, const int64_t *vtx_base, const int64_t *arc_base,
+                              const int32_t *out_off, const int32_t *out_adj, const int32_t *in_off,
+                              const int32_t *in_adj, int32_t *labels_out, const scc_options_t *opt,
+                              scc_stats_t *stats);
+
+/* Load the learned round policy: a float32 MLP 5 -> 32 -> 32 -> 8 with ReLU,
+ * weights as one host blob [W1(32x5), b1(32), W2(32x32), b2(32), W3(8x32),
+ * b3(8)] (row-major, out x in), n_floats = 1512.  The 8 outputs score
+ * 4 VGC budgets x 2 frontier modes for the next round.  The blob is copied.
+ * Non-finite weights are rejected with SCC_EPOLICY. */
+scc_status scc_policy_load(scc_ctx_t *ctx, const float *weights, int64_t n_floats);
+
+/* Evaluate the loaded policy on host features (float32[rows*5]) with the
+ * device inference kernel; writes float32[rows*8] scores to host `scores`.
+ * Test hook for parity with a CPU forward pass. */
+scc_status scc_policy_eval(scc_ctx_t *ctx, const float *feats, int32_t rows, float *scores);
+
+/* Hash bag self test (Section 3.3).  keys: device uint64[n] (any values);
+ * every key is inserted by a concurrent wave-aggregated Insert in `rounds`
+ * rounds of the round-robin split keys[i] -> round i % rounds; after each
+ * round ExtractAll appends the bag's content to out (device uint64[n]).
+ * *n_out (host) receives the number extracted, which equals n when the
+ * structure is correct.  Stats report chunk advances.  Test hook. */
+scc_status scc_bag_selftest(scc_ctx_t *ctx, const uint64_t *keys, int64_t n, int32_t rounds, uint64_t *out,
+                            int64_t *n_out, const scc_options_t *opt, scc_stats_t *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIPSCC_H */

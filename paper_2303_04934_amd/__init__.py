@@ -1,0 +1,199 @@
+"""hipscc: SCC and reachability on one MI355X (gfx950) via a C-ABI HIP library.
+
+Thin Python binding: it only marshals torch device tensors (memory and
+streams) into the C ABI of ``include/hipscc.h``; every step of the method runs
+in the library's HIP kernels.  Importing works without a GPU; calls need one
+and raise if the library is not built.
+
+    import paper_2303_04934_amd as scc
+    dg = scc.to_device(graph)          # graph: n, m, out_off, out_adj, in_off, in_adj
+    labels = scc.scc_labels(dg)        # int32 [n], min vertex id of each SCC
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _native
+from ._native import POLICY_FLOATS, STATUS_NAMES, Options, Stats
+
+__all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_reach",
+           "scc_labels_batched", "bag_selftest", "policy_load", "policy_eval", "version", "POLICY_FLOATS"]
+
+
+class SccError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, code), msg))
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class DeviceGraph:
+    n: int
+    m: int
+    out_off: object
+    out_adj: object
+    in_off: object
+    in_adj: object
+
+    def c_struct(self):
+        return _native.Graph(self.n, self.m, self.out_off.data_ptr(), self.out_adj.data_ptr() if self.m else 0,
+                             self.in_off.data_ptr(), self.in_adj.data_ptr() if self.m else 0)
+
+
+def to_device(g, device="cuda") -> DeviceGraph:
+    """Copy a host graph (numpy int32 CSR + transposed CSR) to device tensors."""
+    torch = _torch()
+
+    def up(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+    return DeviceGraph(int(g.n), int(g.m), up(g.out_off), up(g.out_adj), up(g.in_off), up(g.in_adj))
+
+
+_contexts = {}
+
+
+def _ctx(device_index: int, stream_handle: int):
+    key = (device_index, stream_handle)
+    c = _contexts.get(key)
+    if c is None:
+        lib = _native.load()
+        p = ctypes.c_void_p()
+        rc = lib.scc_create(ctypes.byref(p), device_index, ctypes.c_void_p(stream_handle))
+        if rc != 0:
+            raise SccError(rc, "scc_create failed on device %d" % device_index)
+        c = _contexts[key] = p
+    return c
+
+
+def _current(t):
+    torch = _torch()
+    dev = t.device.index if t.device.index is not None else torch.cuda.current_device()
+    s = torch.cuda.current_stream(dev).cuda_stream
+    return _ctx(dev, s)
+
+
+def _check(lib, ctx, rc):
+    if rc != 0:
+        raise SccError(rc, lib.scc_last_error(ctx).decode(errors="replace"))
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _native.load().scc_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def version() -> str:
+    return _native.load().scc_version().decode()
+
+
+def scc_labels(dg: DeviceGraph, options: Options | None = None, return_stats: bool = False, out=None):
+    """SCC labels (min vertex id per SCC) of a device graph, int32 tensor [n]."""
+    torch = _torch()
+    lib = _native.load()
+    ctx = _current(dg.out_off)
+    if out is None:
+        out = torch.empty(max(dg.n, 1), dtype=torch.int32, device=dg.out_off.device)
+    st = Stats()
+    g = dg.c_struct()
+    rc = lib.scc_labels(ctx, ctypes.byref(g), out.data_ptr(), ctypes.byref(options) if options else None,
+                        ctypes.byref(st))
+    _check(lib, ctx, rc)
+    out = out[:dg.n]
+    return (out, st.as_dict()) if return_stats else out
+
+
+def scc_reach(dg: DeviceGraph, sources, labels, direction: int = 0, capacity: int | None = None,
+              options: Options | None = None, return_stats: bool = False):
+    """Reachability pairs (vertex, source index) as an int32 tensor [count, 2],
+    in unspecified order.  Arcs are used only between equal, non-negative labels."""
+    torch = _torch()
+    lib = _native.load()
+    dev = dg.out_off.device
+    sources = torch.as_tensor(sources, dtype=torch.int32, device=dev).contiguous()
+    labels = torch.as_tensor(labels, dtype=torch.int32, device=dev).contiguous()
+    ctx = _current(dg.out_off)
+    k = int(sources.numel())
+    if capacity is None:
+        capacity = max(16, k * max(dg.n, 1)) if k * max(dg.n, 1) < (1 << 26) else (1 << 26)
+    pairs = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=dev)
+    cnt = ctypes.c_int64(0)
+    st = Stats()
+    g = dg.c_struct()
+    rc = lib.scc_reach(ctx, ctypes.byref(g), direction, sources.data_ptr() if k else None, k,
+                       labels.data_ptr() if k else None, pairs.data_ptr(), capacity, ctypes.byref(cnt),
+                       ctypes.byref(options) if options else None, ctypes.byref(st))
+    if rc == _native.SCC_ECAPACITY:
+        need = int(cnt.value)
+        return scc_reach(dg, sources, labels, direction, need, options, return_stats)
+    _check(lib, ctx, rc)
+    out = pairs[:cnt.value]
+    return (out, st.as_dict()) if return_stats else out
+
+
+def scc_labels_batched(vtx_base, arc_base, out_off, out_adj, in_off, in_adj, options: Options | None = None,
+                       return_stats: bool = False):
+    """SCC labels of many graphs at once (local ids); see scc_labels_batched in hipscc.h."""
+    torch = _torch()
+    lib = _native.load()
+    vb = np.ascontiguousarray(vtx_base, dtype=np.int64)
+    ab = np.ascontiguousarray(arc_base, dtype=np.int64)
+    G = len(vb) - 1
+    ctx = _current(out_off)
+    out = torch.empty(max(int(vb[-1]), 1), dtype=torch.int32, device=out_off.device)
+    st = Stats()
+    rc = lib.scc_labels_batched(ctx, G, vb.ctypes.data, ab.ctypes.data, out_off.data_ptr(),
+                                out_adj.data_ptr() if out_adj.numel() else None, in_off.data_ptr(),
+                                in_adj.data_ptr() if in_adj.numel() else None, out.data_ptr(),
+                                ctypes.byref(options) if options else None, ctypes.byref(st))
+    _check(lib, ctx, rc)
+    out = out[:int(vb[-1])]
+    return (out, st.as_dict()) if return_stats else out
+
+
+def bag_selftest(keys, rounds: int = 1, options: Options | None = None, return_stats: bool = False):
+    """Insert every key into the hash bag (round robin over `rounds` rounds) and
+    return what the ExtractAll calls returned (uint64 keys as int64)."""
+    torch = _torch()
+    lib = _native.load()
+    keys = keys.contiguous()
+    ctx = _current(keys)
+    n = int(keys.numel())
+    out = torch.empty(max(n, 1), dtype=torch.int64, device=keys.device)
+    cnt = ctypes.c_int64(0)
+    st = Stats()
+    rc = lib.scc_bag_selftest(ctx, keys.data_ptr() if n else None, n, rounds, out.data_ptr(), ctypes.byref(cnt),
+                              ctypes.byref(options) if options else None, ctypes.byref(st))
+    _check(lib, ctx, rc)
+    out = out[:cnt.value]
+    return (out, st.as_dict()) if return_stats else out
+
+
+def policy_load(weights, device_index: int = 0):
+    torch = _torch()
+    lib = _native.load()
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    ctx = _ctx(device_index, torch.cuda.current_stream(device_index).cuda_stream)
+    _check(lib, ctx, lib.scc_policy_load(ctx, w.ctypes.data, w.size))
+
+
+def policy_eval(feats, device_index: int = 0):
+    torch = _torch()
+    lib = _native.load()
+    x = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 5)
+    out = np.empty((x.shape[0], 8), np.float32)
+    ctx = _ctx(device_index, torch.cuda.current_stream(device_index).cuda_stream)
+    _check(lib, ctx, lib.scc_policy_eval(ctx, x.ctypes.data, x.shape[0], out.ctypes.data))
+    return out

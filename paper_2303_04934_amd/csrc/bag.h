@@ -1,0 +1,146 @@
+// Parallel hash bag (Section 3.3, Figure 5 / Figure 6), wavefront edition.
+//
+// The bag is a preallocated array split into chunks of doubling size: chunk 0
+// holds [0, lambda), chunk i >= 1 holds [lambda * 2^(i-1), lambda * 2^i).  The
+// current chunk r only grows.  Inserts land in chunk r; a sampled estimate of
+// its load moves r forward (Section 3.3: each insert is sampled with
+// probability sigma / (alpha * chunk size); when a chunk has collected sigma
+// samples, a CAS advances r).  ExtractAll packs the used prefix [0, tail[r])
+// and clears it, so its cost is proportional to the bag's content plus lambda
+// (Theorem 1).
+//
+// GPU form.  The paper's insert CASes a random slot and probes linearly.  Here
+// a wavefront inserts its elements together: each chunk is cut into stripes
+// of kStripe slots with one fill counter each; the wave picks a random stripe
+// of chunk r and reserves room for all its elements with one fetch-and-add on
+// that counter, spilling the remainder to the next stripe (the probe).  After
+// kappa probes the insert forces a chunk advance, as the paper's probe limit
+// does.  A stripe's valid slots are exactly [0, min(count, kStripe)), so
+// ExtractAll reads counters instead of scanning for empty slots, and clearing
+// resets counters only.  Random stripe choice spreads the atomics over many
+// addresses; sampling keeps the chunk advance off the common path.
+#pragma once
+
+#include "device.h"
+
+namespace hipscc {
+
+constexpr int kStripeLog2 = 6;
+constexpr int kStripe = 1 << kStripeLog2;
+constexpr int kMaxChunks = 40;
+
+// Control words of one bag, in device memory.
+struct BagCtl {
+    uint32_t r;                    // current chunk
+    uint32_t done_blocks;          // ExtractAll's last-block ticket
+    uint32_t overflow;             // set when the last chunk is full
+    uint32_t advances;             // chunk advances (statistics)
+    uint32_t sample[kMaxChunks];   // samples taken per chunk
+};
+
+struct Bag {
+    uint64_t *slots;     // capacity = lambda << (nchunks - 1) entries
+    uint32_t *cnt;       // one fill counter per stripe
+    BagCtl *ctl;
+    uint32_t lam_log2;   // log2(lambda), lambda >= kStripe
+    uint32_t nchunks;
+    uint32_t sigma;
+    uint32_t kappa;
+    float alpha;
+    uint32_t salt;       // varies per round: decorrelates stripe choice and sampling
+};
+
+__host__ __device__ __forceinline__ uint64_t bag_chunk_lo(const Bag &B, uint32_t i) {
+    return i == 0 ? 0ull : (1ull << (B.lam_log2 + i - 1));
+}
+__host__ __device__ __forceinline__ uint64_t bag_chunk_hi(const Bag &B, uint32_t i) {
+    return 1ull << (B.lam_log2 + i);
+}
+
+// Wave-cooperative Insert.  Every lane of the wave must call it (uniform
+// control flow); lanes with has == true contribute element e.  `wseq` is a
+// per-wave sequence number (wave-uniform) used to draw the random stripe.
+// Returns the number of elements this wave inserted.
+__device__ __forceinline__ int bag_insert_wave(const Bag &B, bool has, uint64_t e, uint32_t wave_gid,
+                                               uint32_t &wseq) {
+    bool pending = has;
+    int inserted = popc64(ballot(has));
+    uint64_t mask = ballot(pending);
+    while (mask) {
+        const int k = popc64(mask);
+        const int my = rank_below(mask);
+        uint32_t r = ld_relaxed(&B.ctl->r);
+        if (r >= B.nchunks) r = B.nchunks - 1;
+        const bool last = (r + 1 >= B.nchunks);
+        const uint64_t lo = bag_chunk_lo(B, r), hi = bag_chunk_hi(B, r);
+        const uint64_t size = hi - lo;
+        // Sampling (Section 3.3): rate sigma / (alpha * size).
+        bool advanced = false;
+        if (!last) {
+            double rate = (double)B.sigma / ((double)B.alpha * (double)size);
+            uint32_t thr = rate >= 1.0 ? 0xffffffffu : (uint32_t)(rate * 4294967296.0);
+            uint32_t coin = (uint32_t)mix64(e ^ ((uint64_t)B.salt << 32) ^ 0x5851F42D4C957F2Dull);
+            const int ns = popc64(ballot(pending && coin < thr));
+            if (ns > 0) {
+                uint32_t adv = 0;
+                if (lane_id() == 0) {
+                    uint32_t old = atomicAdd(&B.ctl->sample[r], (uint32_t)ns);
+                    if (old + (uint32_t)ns >= B.sigma) {
+                        // try_resize: only one CAS from r wins
+                        if (atomicCAS(&B.ctl->r, r, r + 1) == r) atomicAdd(&B.ctl->advances, 1u);
+                        adv = 1;
+                    }
+                }
+                advanced = wave_bcast_u(adv, 0) != 0;
+            }
+        }
+        if (advanced) {
+            mask = ballot(pending);
+            continue;  // insert again into the new chunk
+        }
+        const uint32_t nst = (uint32_t)(size >> kStripeLog2);
+        const uint32_t st0 = (uint32_t)(lo >> kStripeLog2);
+        uint32_t st = (uint32_t)(mix64(((uint64_t)wave_gid << 32) ^ (uint64_t)(wseq++) ^
+                                       ((uint64_t)B.salt << 20)) % nst);
+        int placed = 0;
+        uint32_t probes = 0;
+        bool spill = false;
+        while (placed < k) {
+            uint32_t o = 0;
+            if (lane_id() == 0) o = atomicAdd(&B.cnt[st0 + st], (uint32_t)(k - placed));
+            o = wave_bcast_u(o, 0);
+            int avail = o < (uint32_t)kStripe ? (int)((uint32_t)kStripe - o) : 0;
+            if (avail > k - placed) avail = k - placed;
+            if (pending && my >= placed && my < placed + avail) {
+                B.slots[((uint64_t)(st0 + st) << kStripeLog2) + o + (uint32_t)(my - placed)] = e;
+            }
+            placed += avail;
+            if (placed < k) {
+                st = (st + 1 == nst) ? 0 : st + 1;
+                probes++;
+                if (!last && probes > B.kappa) {
+                    if (lane_id() == 0) {
+                        if (atomicCAS(&B.ctl->r, r, r + 1) == r) atomicAdd(&B.ctl->advances, 1u);
+                    }
+                    spill = true;
+                    break;
+                }
+                if (last && probes >= nst) {
+                    if (lane_id() == 0) atomicOr(&B.ctl->overflow, 1u);
+                    spill = false;
+                    placed = k;  // give up: the host sees the overflow flag
+                    inserted = 0;
+                    break;
+                }
+            }
+        }
+        if (pending && my < placed) pending = false;
+        if (!spill) {
+            pending = false;
+        }
+        mask = ballot(pending);
+    }
+    return inserted;
+}
+
+}  // namespace hipscc

@@ -1,0 +1,660 @@
+// hipscc kernels (gfx950).  All kernels are launched by runtime.hip.
+#pragma once
+
+#include "bag.h"
+#include "device.h"
+
+namespace hipscc {
+
+// Per-search round control block in device memory.  Rounds alternate between
+// parity 0 and 1 so that one round's counters can be reset while the next
+// round's are in use.
+struct RoundCtl {
+    uint32_t nF[2];        // frontier sizes
+    uint32_t work[2];      // dynamic work counters of the expand kernel
+    uint32_t heavy_n[2];   // entries deferred to the edge-parallel kernel
+    uint32_t err;          // kErr* bits
+    uint32_t rounds;       // rounds with a non-empty frontier
+    uint32_t k;            // sources selected for the batch
+    uint32_t fin;          // vertices finished by the last relabel
+    uint32_t first;        // first active permutation position (batch 1)
+    uint32_t emit;         // pairs emitted by scc_reach
+    uint32_t nscc;         // canonical representatives
+    uint32_t trimmed;
+    uint32_t pad[2];
+    unsigned long long expanded, arcs, attempts, claims, inserts, pairs;
+};
+
+constexpr uint32_t kErrTable = 1u;      // reach table probe limit exceeded
+constexpr uint32_t kErrCapacity = 2u;   // frontier / heavy list capacity exceeded
+constexpr uint32_t kErrUnfinished = 4u; // a vertex had no SCC key at the end
+
+constexpr int kQcap = 512;  // local queue entries per wave (LDS)
+constexpr int kQmask = kQcap - 1;
+constexpr int kStepArcs = 256;  // arcs a wave commits to per local-search step
+
+enum { kSingle = 0, kMulti = 1 };
+
+// One reachability search (one direction).  kSingle claims vertices in a
+// visited bitmap whose bits were pre-set for every vertex outside the search's
+// subproblem; kMulti claims (vertex, source) pairs in the reach table.
+struct Search {
+    const int32_t *off;
+    const int32_t *adj;
+    const int32_t *label;   // kMulti: arc (u, w) is used iff label[w] == label of the source
+    uint32_t *vis;          // kSingle
+    uint64_t *table;        // kMulti
+    uint64_t tmask;
+    uint32_t probe_limit;
+    const int32_t *srclab;  // kMulti: label of source j
+    uint64_t *F;            // packed frontier (read by expand, rewritten by extract)
+    uint64_t *heavy;        // deferred high-degree entries
+    uint64_t fcap;          // capacity of F and heavy
+    Bag bag;
+    RoundCtl *rc;
+    int32_t par;
+    int32_t tau;            // <= 1: plain frontier BFS
+    int32_t seeds;          // 0: automatic
+    int32_t heavy_deg;
+};
+
+// ------------------------------------------------------------- utilities ----
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__device__ __forceinline__ void wave_add_u32(uint32_t *ctr, bool pred) {
+    uint64_t m = ballot(pred);
+    if (m && lane_id() == 0) atomicAdd(ctr, (uint32_t)popc64(m));
+}
+
+// ------------------------------------------------------------------ trim ----
+// Section 4.1: a vertex with zero in- or out-degree is a singleton SCC.
+// Finished vertices store ~key (negative); key = v here.
+__global__ void k_trim(int32_t n, const int32_t *out_off, const int32_t *in_off, int32_t *label, int32_t do_trim,
+                       RoundCtl *rc) {
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        int64_t v = v0 + threadIdx.x;
+        bool t = false;
+        if (v < n) {
+            t = do_trim && (out_off[v + 1] == out_off[v] || in_off[v + 1] == in_off[v]);
+            label[v] = t ? ~(int32_t)v : 0;
+        }
+        wave_add_u32(&rc->trimmed, t);
+    }
+}
+
+// ----------------------------------------------------- source selection ----
+// Batch 1 of Algorithm 1 is one random vertex; among active vertices, take the
+// first one in permutation order.
+__global__ void k_first_active(Perm P, const int32_t *label, RoundCtl *rc) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < P.n; j += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t v = perm_apply(P, (uint32_t)j);
+        if (label[v] >= 0) atomicMin(&rc->first, (uint32_t)j);
+    }
+}
+
+// Sources of one batch: the active vertices among permutation positions
+// [p0, p1) (Algorithm 1: F = P_i intersect V').
+__global__ void k_select_sources(Perm P, uint32_t p0, uint32_t p1, const int32_t *label, int32_t *srcvert,
+                                 int32_t *srclab, RoundCtl *rc) {
+    for (int64_t j0 = p0 + blockIdx.x * (int64_t)blockDim.x; j0 < p1; j0 += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = j0 + threadIdx.x;
+        int32_t v = -1, l = -1;
+        if (j < p1) {
+            v = (int32_t)perm_apply(P, (uint32_t)j);
+            l = label[v];
+        }
+        bool act = l >= 0;
+        uint64_t m = ballot(act);
+        uint32_t base = 0;
+        if (m && lane_id() == 0) base = atomicAdd(&rc->k, (uint32_t)popc64(m));
+        base = wave_bcast_u(base, 0);
+        if (act) {
+            uint32_t idx = base + rank_below(m);
+            srcvert[idx] = v;
+            srclab[idx] = l;
+        }
+    }
+}
+
+// ---------------------------------------------------------- reach claims ----
+__device__ __forceinline__ bool claim_bit(uint32_t *vis, int32_t w) {
+    uint32_t bit = 1u << (w & 31);
+    uint32_t *p = vis + (w >> 5);
+    if (ld_relaxed(p) & bit) return false;
+    return (atomicOr(p, bit) & bit) == 0;
+}
+
+// 1: new pair claimed; 0: pair already present; -1: probe limit exceeded.
+__device__ __forceinline__ int claim_pair(uint64_t *T, uint64_t mask, uint32_t limit, uint64_t key) {
+    uint64_t h = mix64(key) & mask;
+    for (uint32_t p = 0; p <= limit; p++) {
+        uint64_t cur = ld_relaxed64(T + h);
+        if (cur == key) return 0;
+        if (cur == kEmpty64) {
+            unsigned long long old = atomicCAS((unsigned long long *)(T + h), (unsigned long long)kEmpty64,
+                                               (unsigned long long)key);
+            if (old == kEmpty64) return 1;
+            if (old == key) return 0;
+        }
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ bool table_contains(const uint64_t *T, uint64_t mask, uint32_t limit, uint64_t key) {
+    uint64_t h = mix64(key) & mask;
+    for (uint32_t p = 0; p <= limit; p++) {
+        uint64_t cur = T[h];
+        if (cur == key) return true;
+        if (cur == kEmpty64) return false;
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+// Seed the search: single source.  Bit v of vis = "not available" (outside the
+// subproblem L), plus the source itself, which is claimed up front.
+__global__ void k_premark(int32_t n, const int32_t *label, int32_t L, int32_t s, uint32_t *vis) {
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        int64_t v = v0 + threadIdx.x;
+        bool blocked = v >= n || label[v] != L || v == s;
+        uint64_t m = ballot(blocked);
+        int l = lane_id();
+        // lanes 0 and 32 write the two 32-bit words covering this wave's 64 vertices
+        int64_t wbase = (v0 + (threadIdx.x & ~63)) >> 5;
+        if (l == 0 && (wbase << 5) < n) vis[wbase] = (uint32_t)m;
+        if (l == 32 && ((wbase + 1) << 5) < n) vis[wbase + 1] = (uint32_t)(m >> 32);
+    }
+}
+
+__global__ void k_seed_single(int32_t s, uint64_t *F, RoundCtl *rc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        F[0] = pair_key(s, 0);
+        rc->nF[0] = 1;
+        rc->nF[1] = 0;
+        rc->work[0] = rc->work[1] = 0;
+        rc->heavy_n[0] = rc->heavy_n[1] = 0;
+        rc->rounds = 0;
+    }
+}
+
+// Multi-source seed: claim (s_j, j) and put it in the frontier.
+__global__ void k_seed_multi(const int32_t *srcvert, uint64_t *T, uint64_t mask, uint32_t limit, uint64_t *F,
+                             RoundCtl *rc) {
+    const uint32_t k = rc->k;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
+        uint64_t key = pair_key(srcvert[j], j);
+        if (claim_pair(T, mask, limit, key) < 0) atomicOr(&rc->err, kErrTable);
+        F[j] = key;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rc->nF[0] = k;
+        rc->nF[1] = 0;
+        rc->work[0] = rc->work[1] = 0;
+        rc->heavy_n[0] = rc->heavy_n[1] = 0;
+        rc->rounds = 0;
+    }
+}
+
+// ---------------------------------------------------------------- expand ----
+// One frontier round with vertical granularity control (Section 3.1-3.2).
+//
+// Each wavefront takes a group of frontier entries and runs one bounded local
+// search seeded with all of them: its FIFO local queue lives in LDS; each step
+// the wave takes whole entries from the queue head (as many as fit in
+// kStepArcs arcs), spreads their arcs over its 64 lanes, and claims the
+// targets.  Every examined arc counts against the budget tau * (seeds), as in
+// Section 3.2 (successful or not).  Newly claimed entries go to the local
+// queue while it has room, otherwise straight to the hash bag.  When the
+// budget is spent or the queue is empty, what is left in the queue is
+// inserted into the bag, i.e. the next frontier (Section 3.2).  With tau <= 1
+// nothing is searched locally and this is one plain BFS round (Algorithm 2/3).
+// Entries with more than heavy_deg arcs are deferred to k_expand_heavy, which
+// spreads one adjacency list over the whole grid (Section 3.2: vertices with
+// more than tau neighbours are processed edge-parallel).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_expand(Search S) {
+    __shared__ uint64_t Qs[kWavesPerBlock][kQcap];
+    __shared__ int32_t Sx[kWavesPerBlock][4][kWave];
+    const int wv = threadIdx.x / kWave;
+    const int lane = lane_id();
+    uint64_t *Q = Qs[wv];
+    int32_t *sexcl = Sx[wv][0];
+    int32_t *sbeg = Sx[wv][1];
+    int32_t *ssrc = Sx[wv][2];
+    int32_t *slab = Sx[wv][3];
+    RoundCtl *rc = S.rc;
+    uint32_t nF = ld_relaxed(&rc->nF[S.par]);
+    if (nF == 0) return;
+    if (nF > S.fcap) nF = (uint32_t)S.fcap;  // overflow was flagged by ExtractAll
+    if (blockIdx.x == 0 && threadIdx.x == 0) rc->rounds += 1;
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + wv;
+    uint32_t G = (uint32_t)S.seeds;
+    if (G == 0) {
+        G = (nF + 2 * nwaves - 1) / (2 * nwaves);
+        if (G > 64) G = 64;
+        if (G < 1) G = 1;
+    }
+    const uint32_t ngroups = (nF + G - 1) / G;
+    const bool vgc = S.tau > 1;
+    uint32_t wseq = 0;
+    unsigned long long c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
+
+    uint32_t grp = wave_gid;
+    while (grp < ngroups) {
+        const uint32_t start = grp * G;
+        const int cnt = (int)((nF - start) < G ? (nF - start) : G);
+        if (lane < cnt) Q[lane] = S.F[start + lane];
+        int head = 0, tail = cnt;
+        long long t = 0;
+        const long long budget = vgc ? (long long)S.tau * cnt : 0;
+        wave_lds_sync();
+        while (head < tail && (!vgc || t < budget)) {
+            const int avail = tail - head;
+            const int k = avail < kWave ? avail : kWave;
+            uint64_t e = 0;
+            int32_t d = 0, beg = 0, lab = 0;
+            uint32_t s = 0;
+            if (lane < k) {
+                e = Q[(head + lane) & kQmask];
+                const int32_t u = key_vertex(e);
+                s = key_source(e);
+                beg = S.off[u];
+                d = S.off[u + 1] - beg;
+                if (MODE == kMulti) lab = S.srclab[s];
+            }
+            const bool hv = lane < k && d > S.heavy_deg;
+            const int dd = hv ? 0 : d;
+            const int incl = wave_incl_scan(dd);
+            const int excl = incl - dd;
+            // whole entries whose arcs start within the step's arc window
+            const uint64_t cm = ballot(lane < k && excl < kStepArcs);
+            const int kk = popc64(cm);
+            const bool mine = lane < kk;
+            const uint64_t hm = ballot(hv && mine);
+            if (hm) {
+                uint32_t hb = 0;
+                if (lane == 0) hb = atomicAdd(&rc->heavy_n[S.par], (uint32_t)popc64(hm));
+                hb = wave_bcast_u(hb, 0);
+                if (hv && mine) {
+                    uint64_t pos = (uint64_t)hb + (uint64_t)rank_below(hm);
+                    if (pos < S.fcap) S.heavy[pos] = e;
+                    else atomicOr(&rc->err, kErrCapacity);
+                }
+            }
+            const int D = wave_bcast(incl, kk - 1);
+            if (mine) {
+                sexcl[lane] = excl;
+                sbeg[lane] = beg;
+                ssrc[lane] = (int32_t)s;
+                slab[lane] = lab;
+            }
+            head += kk;
+            t += D;
+            c_exp += (mine && !hv) ? 1 : 0;
+            wave_lds_sync();
+            for (int base = 0; base < D; base += kWave) {
+                const int a = base + lane;
+                bool claimed = false;
+                uint64_t ne = 0;
+                if (a < D) {
+                    int lo = 0, hi = kk - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sexcl[mid] <= a) lo = mid; else hi = mid - 1;
+                    }
+                    const int32_t w = S.adj[sbeg[lo] + (a - sexcl[lo])];
+                    const uint32_t src = (uint32_t)ssrc[lo];
+                    c_arcs++;
+                    if (MODE == kSingle) {
+                        c_att++;
+                        claimed = claim_bit(S.vis, w);
+                    } else {
+                        if (S.label[w] == slab[lo]) {
+                            c_att++;
+                            const int c = claim_pair(S.table, S.tmask, S.probe_limit, pair_key(w, src));
+                            if (c < 0) atomicOr(&rc->err, kErrTable);
+                            claimed = c == 1;
+                        }
+                    }
+                    ne = pair_key(w, src);
+                }
+                const uint64_t cmask = ballot(claimed);
+                if (cmask == 0) continue;
+                const int nc = popc64(cmask);
+                c_claims += claimed ? 1 : 0;
+                const int room = vgc ? kQcap - (tail - head) : 0;
+                const int r = rank_below(cmask);
+                if (claimed && r < room) Q[(tail + r) & kQmask] = ne;
+                tail += nc < room ? nc : room;
+                c_ins += (unsigned long long)bag_insert_wave(S.bag, claimed && r >= room, ne, wave_gid, wseq);
+            }
+            wave_lds_sync();
+        }
+        // flush the rest of the local queue into the next frontier
+        for (int i = head; i < tail; i += kWave) {
+            const bool h = i + lane < tail;
+            const uint64_t e = h ? Q[(i + lane) & kQmask] : 0;
+            c_ins += (unsigned long long)bag_insert_wave(S.bag, h, e, wave_gid, wseq);
+        }
+        wave_lds_sync();
+        uint32_t nxt = 0;
+        if (lane == 0) nxt = atomicAdd(&rc->work[S.par], 1u) + nwaves;
+        grp = wave_bcast_u(nxt, 0);
+    }
+    c_exp = wave_sum_u64(c_exp);
+    c_arcs = wave_sum_u64(c_arcs);
+    c_att = wave_sum_u64(c_att);
+    c_claims = wave_sum_u64(c_claims);
+    if (lane == 0) {
+        atomicAdd(&rc->expanded, c_exp);
+        atomicAdd(&rc->arcs, c_arcs);
+        atomicAdd(&rc->attempts, c_att);
+        atomicAdd(&rc->claims, c_claims);
+        atomicAdd(&rc->inserts, c_ins);
+    }
+}
+
+// Edge-parallel expansion of the deferred high-degree entries: every wave of
+// the grid takes a 64-arc slice of each list in turn; claims go to the bag.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_expand_heavy(Search S) {
+    RoundCtl *rc = S.rc;
+    uint32_t nh = ld_relaxed(&rc->heavy_n[S.par]);
+    if (nh == 0) return;
+    if (nh > S.fcap) nh = (uint32_t)S.fcap;
+    const int lane = lane_id();
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    uint32_t wseq = 0x8000u;
+    unsigned long long c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
+    for (uint32_t h = 0; h < nh; h++) {
+        const uint64_t e = S.heavy[h];
+        const int32_t u = key_vertex(e);
+        const uint32_t src = key_source(e);
+        const int32_t beg = S.off[u];
+        const int32_t d = S.off[u + 1] - beg;
+        const int32_t lab = (MODE == kMulti) ? S.srclab[src] : 0;
+        if (wave_gid == h % nwaves && lane == 0) c_exp++;
+        for (int64_t base = (int64_t)wave_gid * kWave; base < d; base += (int64_t)nwaves * kWave) {
+            const int64_t a = base + lane;
+            bool claimed = false;
+            uint64_t ne = 0;
+            if (a < d) {
+                const int32_t w = S.adj[beg + a];
+                c_arcs++;
+                if (MODE == kSingle) {
+                    c_att++;
+                    claimed = claim_bit(S.vis, w);
+                } else if (S.label[w] == lab) {
+                    c_att++;
+                    const int c = claim_pair(S.table, S.tmask, S.probe_limit, pair_key(w, src));
+                    if (c < 0) atomicOr(&rc->err, kErrTable);
+                    claimed = c == 1;
+                }
+                ne = pair_key(w, src);
+            }
+            c_claims += claimed ? 1 : 0;
+            c_ins += (unsigned long long)bag_insert_wave(S.bag, claimed, ne, wave_gid, wseq);
+        }
+    }
+    c_exp = wave_sum_u64(c_exp);
+    c_arcs = wave_sum_u64(c_arcs);
+    c_att = wave_sum_u64(c_att);
+    c_claims = wave_sum_u64(c_claims);
+    if (lane == 0) {
+        if (c_exp) atomicAdd(&rc->expanded, c_exp);
+        atomicAdd(&rc->arcs, c_arcs);
+        atomicAdd(&rc->attempts, c_att);
+        atomicAdd(&rc->claims, c_claims);
+        atomicAdd(&rc->inserts, c_ins);
+    }
+}
+
+// --------------------------------------------------------- ExtractAll ----
+// Packs the bag's used prefix [0, tail[r]) into the frontier array F and
+// clears it (Section 3.3: ExtractAll emits and removes all elements).  A wave
+// handles 64 stripes: a prefix sum of their counts gives each stripe's output
+// offset and one atomic per wave reserves the wave's range.  The last block
+// to finish resets the bag's chunk state and this round's counters.
+__global__ __launch_bounds__(kBlock) void k_bag_extract(Bag B, uint64_t *F, uint64_t fcap, RoundCtl *rc, int par) {
+    __shared__ bool last;
+    const int lane = lane_id();
+    uint32_t r = ld_relaxed(&B.ctl->r);
+    if (r >= B.nchunks) r = B.nchunks - 1;
+    const uint64_t nst = bag_chunk_hi(B, r) >> kStripeLog2;
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    for (uint64_t sb = (uint64_t)wave_gid * kWave; sb < nst; sb += (uint64_t)nwaves * kWave) {
+        const uint64_t st = sb + lane;
+        uint32_t c = 0;
+        if (st < nst) {
+            c = B.cnt[st];
+            if (c > (uint32_t)kStripe) c = kStripe;
+        }
+        const int incl = wave_incl_scan((int)c);
+        const int tot = wave_bcast(incl, kWave - 1);
+        if (tot == 0) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&rc->nF[par ^ 1], (uint32_t)tot);
+        base = wave_bcast_u(base, 0);
+        const int excl = incl - (int)c;
+        for (int j = 0; j < kWave; j++) {
+            const int cj = wave_bcast((int)c, j);
+            if (cj == 0) continue;
+            const uint64_t oj = (uint64_t)base + (uint64_t)wave_bcast(excl, j);
+            if (lane < cj) {
+                const uint64_t v = B.slots[((sb + j) << kStripeLog2) + lane];
+                if (oj + lane < fcap) F[oj + lane] = v;
+                else atomicOr(&rc->err, kErrCapacity);
+            }
+        }
+        if (st < nst && c) B.cnt[st] = 0;
+    }
+    // ExtractAll also clears the chunk state: the last block does it once
+    // every block has finished reading r.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&B.ctl->done_blocks, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        for (uint32_t i = threadIdx.x; i < B.nchunks && i < (uint32_t)kMaxChunks; i += blockDim.x) B.ctl->sample[i] = 0;
+        if (threadIdx.x == 0) {
+            B.ctl->r = 0;
+            B.ctl->done_blocks = 0;
+            rc->nF[par] = 0;
+            rc->work[par] = 0;
+            rc->heavy_n[par] = 0;
+        }
+    }
+}
+
+// -------------------------------------------------------------- relabel ----
+// Single source (the first SCC, Section 4.2): vertices reached both ways are
+// finished with key s; vertices reached one way move to a new subproblem
+// labelled by the hash of (old label, R_in, R_out) (Algorithm 1).
+__global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, int32_t s, const uint32_t *visF,
+                                const uint32_t *visB, RoundCtl *rc) {
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        bool fin = false;
+        if (v < n && label[v] == L) {
+            const bool f = (visF[v >> 5] >> (v & 31)) & 1u;
+            const bool b = (visB[v >> 5] >> (v & 31)) & 1u;
+            if (f && b) {
+                label[v] = ~s;
+                fin = true;
+            } else if (f || b) {
+                label[v] = relabel_hash(L, b ? sig_term_in(s) : 0ull, f ? sig_term_out(s) : 0ull);
+            }
+        }
+        wave_add_u32(&rc->fin, fin);
+    }
+}
+
+// Multi source, pass 1: accumulate the per-vertex set hashes of R_out (pairs
+// of the forward table) and R_in (backward table), and detect vertices that
+// share a source in both directions (Algorithm 1: R_1 and R_2 intersect).
+__global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, const uint64_t *Tin, uint64_t min_,
+                             uint32_t limit, const int32_t *srcvert, unsigned long long *sig_out,
+                             unsigned long long *sig_in, int32_t *fin) {
+    const uint64_t n_out = mout + 1, n_tot = n_out + min_ + 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_tot; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i < n_out) {
+            const uint64_t key = Tout[i];
+            if (key == kEmpty64) continue;
+            atomicAdd(&sig_out[key_vertex(key)], (unsigned long long)sig_term_out(srcvert[key_source(key)]));
+        } else {
+            const uint64_t key = Tin[i - n_out];
+            if (key == kEmpty64) continue;
+            const int32_t v = key_vertex(key);
+            atomicAdd(&sig_in[v], (unsigned long long)sig_term_in(srcvert[key_source(key)]));
+            if (table_contains(Tout, mout, limit, key)) atomicMin(&fin[v], (int32_t)key_source(key));
+        }
+    }
+}
+
+// Multi source, pass 2: one owner per touched vertex (first to stamp it with
+// this batch's epoch) writes its new label and resets its accumulators; every
+// table slot is cleared for the next batch.
+__global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, uint64_t min_, const int32_t *srcvert,
+                                unsigned long long *sig_out, unsigned long long *sig_in, int32_t *fin,
+                                int32_t *stamp, int32_t epoch, int32_t *label, RoundCtl *rc) {
+    const uint64_t n_out = mout + 1, n_tot = n_out + min_ + 1;
+    for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x; i0 < n_tot; i0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = i0 + threadIdx.x;
+        bool finished = false;
+        if (i < n_tot) {
+            uint64_t *slot = i < n_out ? Tout + i : Tin + (i - n_out);
+            const uint64_t key = *slot;
+            if (key != kEmpty64) {
+                *slot = kEmpty64;
+                const int32_t v = key_vertex(key);
+                if (atomicExch(&stamp[v], epoch) != epoch) {
+                    const int32_t f = fin[v];
+                    if (f != kInf32) {
+                        label[v] = ~srcvert[f];
+                        finished = true;
+                    } else {
+                        label[v] = relabel_hash(label[v], sig_in[v], sig_out[v]);
+                    }
+                    sig_in[v] = 0;
+                    sig_out[v] = 0;
+                    fin[v] = kInf32;
+                }
+            }
+        }
+        wave_add_u32(&rc->fin, finished);
+    }
+}
+
+// ---------------------------------------------------------- canonical ----
+// labels_out[v] = min vertex id of v's SCC: every finished vertex holds ~key
+// with key a member of its SCC; a min-reduction per key then a gather.
+__global__ void k_canon_min(int32_t n, const int32_t *label, int32_t *aux, RoundCtl *rc) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t l = label[v];
+        if (l >= 0) {
+            atomicOr(&rc->err, kErrUnfinished);
+            continue;
+        }
+        const int32_t key = ~l;
+        if (key >= n) {
+            atomicOr(&rc->err, kErrUnfinished);
+            continue;
+        }
+        atomicMin(&aux[key], (int32_t)v);
+    }
+}
+
+__global__ void k_canon_write(int32_t n, const int32_t *label, const int32_t *aux, int32_t *out, RoundCtl *rc) {
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        bool rep = false;
+        if (v < n) {
+            const int32_t l = label[v];
+            const int32_t r = (l < 0 && ~l < n) ? aux[~l] : -1;
+            out[v] = r;
+            rep = r == v;
+        }
+        wave_add_u32(&rc->nscc, rep);
+    }
+}
+
+// ---------------------------------------------------------- reach output ----
+__global__ void k_emit_single(int32_t n, const int32_t *label, int32_t L, const uint32_t *vis, int32_t s,
+                              int32_t *pairs, uint64_t cap, RoundCtl *rc) {
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        const bool hit = v < n && label[v] == L && ((vis[v >> 5] >> (v & 31)) & 1u);
+        const uint64_t m = ballot(hit);
+        uint32_t base = 0;
+        if (m && lane_id() == 0) base = atomicAdd(&rc->emit, (uint32_t)popc64(m));
+        base = wave_bcast_u(base, 0);
+        if (hit) {
+            const uint64_t pos = (uint64_t)base + rank_below(m);
+            if (pos < cap) {
+                pairs[2 * pos] = (int32_t)v;
+                pairs[2 * pos + 1] = 0;
+            }
+        }
+    }
+    (void)s;
+}
+
+__global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, uint64_t cap, RoundCtl *rc) {
+    const uint64_t nt = mask + 1;
+    for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x; i0 < nt; i0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = i0 + threadIdx.x;
+        const uint64_t key = i < nt ? T[i] : kEmpty64;
+        const bool hit = key != kEmpty64;
+        const uint64_t m = ballot(hit);
+        uint32_t base = 0;
+        if (m && lane_id() == 0) base = atomicAdd(&rc->emit, (uint32_t)popc64(m));
+        base = wave_bcast_u(base, 0);
+        if (hit) {
+            const uint64_t pos = (uint64_t)base + rank_below(m);
+            if (pos < cap) {
+                pairs[2 * pos] = key_vertex(key);
+                pairs[2 * pos + 1] = (int32_t)key_source(key);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ bag test ----
+// Inserts keys[i] for i with i % rounds == rr, one element per lane.
+__global__ __launch_bounds__(kBlock) void k_bag_insert_test(const uint64_t *keys, int64_t n, int32_t rounds,
+                                                             int32_t rr, Bag B, RoundCtl *rc) {
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    uint32_t wseq = 0;
+    const int64_t cnt = (n - rr + rounds - 1) / rounds;  // elements of this round
+    unsigned long long ins = 0;
+    for (int64_t b = (int64_t)wave_gid * kWave; b < cnt; b += (int64_t)nwaves * kWave) {
+        const int64_t i = b + lane_id();
+        const bool h = i < cnt;
+        const uint64_t e = h ? keys[i * rounds + rr] : 0;
+        ins += (unsigned long long)bag_insert_wave(B, h, e, wave_gid, wseq);
+    }
+    if (lane_id() == 0 && ins) atomicAdd(&rc->inserts, ins);
+}
+
+__global__ void k_copy_u64(const uint64_t *src, uint64_t *dst, const RoundCtl *rc, int par, uint64_t cap) {
+    const uint32_t n = rc->nF[par];
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n && i < cap; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace hipscc

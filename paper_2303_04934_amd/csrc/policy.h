@@ -1,0 +1,108 @@
+// Learned round policy: a float32 MLP 5 -> 32 -> 32 -> 8 (ReLU) evaluated by
+// one wavefront.  Inputs are per-round frontier statistics; the 8 outputs
+// score (VGC budget class) x (frontier mode).  The policy only picks the
+// schedule of the next round; it never changes which pairs are found.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+namespace hipscc {
+
+constexpr int kPolicyIn = 5;
+constexpr int kPolicyHidden = 32;
+constexpr int kPolicyOut = 8;
+constexpr int kPolicyFloats = kPolicyHidden * kPolicyIn + kPolicyHidden + kPolicyHidden * kPolicyHidden +
+                              kPolicyHidden + kPolicyOut * kPolicyHidden + kPolicyOut;
+// VGC budgets of the four classes; class c with mode m is output 2 c + m.
+constexpr int kPolicyTau[4] = {64, 256, 1024, 4096};
+
+struct Policy {
+    float *w = nullptr;    // device weights
+    float *io = nullptr;   // device scratch for the test hook
+    uint64_t io_cap = 0;   // floats
+    bool loaded = false;
+};
+
+// Forward pass of one feature row per block of one wavefront; weights are
+// staged through LDS.  Row-major weights, out x in.
+__device__ __forceinline__ void policy_forward_wave(const float *__restrict__ W, const float *x, float *out,
+                                                    float *lds_h1, float *lds_h2) {
+    const int l = threadIdx.x & 63;
+    const float *W1 = W;
+    const float *b1 = W1 + kPolicyHidden * kPolicyIn;
+    const float *W2 = b1 + kPolicyHidden;
+    const float *b2 = W2 + kPolicyHidden * kPolicyHidden;
+    const float *W3 = b2 + kPolicyHidden;
+    const float *b3 = W3 + kPolicyOut * kPolicyHidden;
+    if (l < kPolicyHidden) {
+        float a = b1[l];
+        for (int j = 0; j < kPolicyIn; j++) a = fmaf(W1[l * kPolicyIn + j], x[j], a);
+        lds_h1[l] = a > 0.f ? a : 0.f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (l < kPolicyHidden) {
+        float a = b2[l];
+        for (int j = 0; j < kPolicyHidden; j++) a = fmaf(W2[l * kPolicyHidden + j], lds_h1[j], a);
+        lds_h2[l] = a > 0.f ? a : 0.f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (l < kPolicyOut) {
+        float a = b3[l];
+        for (int j = 0; j < kPolicyHidden; j++) a = fmaf(W3[l * kPolicyHidden + j], lds_h2[j], a);
+        out[l] = a;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_policy_rows(const float *W, const float *feats, int32_t rows, float *scores) {
+    __shared__ float h1[kPolicyHidden], h2[kPolicyHidden];
+    const int r = blockIdx.x;
+    if (r >= rows) return;
+    policy_forward_wave(W, feats + (int64_t)r * kPolicyIn, scores + (int64_t)r * kPolicyOut, h1, h2);
+}
+
+inline void policy_release(Policy &p) {
+    if (p.w) (void)hipFree(p.w);
+    if (p.io) (void)hipFree(p.io);
+    p.w = p.io = nullptr;
+    p.io_cap = 0;
+    p.loaded = false;
+}
+
+// 0 ok, 1 wrong size, 2 non-finite weight, 3 HIP failure.
+inline int policy_load(Policy &p, const float *w, int64_t n, hipStream_t s) {
+    if (!w || n != kPolicyFloats) return 1;
+    for (int64_t i = 0; i < n; i++)
+        if (!std::isfinite(w[i])) return 2;
+    if (!p.w && hipMalloc((void **)&p.w, sizeof(float) * kPolicyFloats) != hipSuccess) return 3;
+    if (hipMemcpyAsync(p.w, w, sizeof(float) * kPolicyFloats, hipMemcpyHostToDevice, s) != hipSuccess) return 3;
+    if (hipStreamSynchronize(s) != hipSuccess) return 3;
+    p.loaded = true;
+    return 0;
+}
+
+inline int policy_eval_host(Policy &p, const float *feats, int32_t rows, float *scores, hipStream_t s) {
+    const uint64_t need = (uint64_t)rows * (kPolicyIn + kPolicyOut);
+    if (p.io_cap < need) {
+        if (p.io) (void)hipFree(p.io);
+        p.io = nullptr;
+        p.io_cap = 0;
+        if (hipMalloc((void **)&p.io, sizeof(float) * need) != hipSuccess) return 3;
+        p.io_cap = need;
+    }
+    float *df = p.io, *ds = p.io + (uint64_t)rows * kPolicyIn;
+    if (hipMemcpyAsync(df, feats, sizeof(float) * rows * kPolicyIn, hipMemcpyHostToDevice, s) != hipSuccess) return 3;
+    hipLaunchKernelGGL(k_policy_rows, dim3(rows), dim3(64), 0, s, p.w, df, rows, ds);
+    if (hipGetLastError() != hipSuccess) return 3;
+    if (hipMemcpyAsync(scores, ds, sizeof(float) * rows * kPolicyOut, hipMemcpyDeviceToHost, s) != hipSuccess) return 3;
+    if (hipStreamSynchronize(s) != hipSuccess) return 3;
+    return 0;
+}
+
+}  // namespace hipscc
