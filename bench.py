@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark: SCC labels of a synthetic digraph on one MI355X.
+
+One step = one full scc_labels call (trim, first-SCC searches, every
+multi-source batch, relabels, canonical labels) on a graph already resident
+in HBM.  Prints one JSON line.  ``value`` = input arcs / wall time of a step
+(edges/s).  ``roofline`` covers the dominant kernel (the frontier-expansion
+kernel of the mode that took longest), from its algorithmic bytes and its
+HIP-event time measured over the timed steps.  ``cpu_baseline`` times the
+sequential Tarjan oracle on the same graph on one host core.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload rmat_s24_ef16]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SCC wall time + traversed edges/s and HBM GB/s; learned/batched vs plain GPU"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "torus1000_p0.5": (0, "2-D torus 1000x1000, each of the 4 neighbour arcs kept with p=0.5"),
+    "rmat_s24_ef16": (1, "R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), self loops and "
+                         "duplicates removed, ids randomly permuted"),
+    "knn_10M_k5": (2, "directed 5-NN graph of 1e7 points, mixture of 1000 isotropic Gaussians (sigma .01) "
+                      "in the unit cube, ties to the lower id"),
+    "grid10000_p0.5": (3, "2-D grid 10000x10000 (no wrap), each neighbour arc kept with p=0.5"),
+}
+KERNEL_NAMES = ["hipscc::k_expand<0>", "hipscc::k_expand<1>", "hipscc::k_pull"]
+KERNEL_SHORT = ["k_expand0", "k_expand1", "k_pull"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2303_04934_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, mode):
+    """Counter-measured HBM bytes per launch from profiles/, if taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (KERNEL_SHORT[mode], workload))
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(g, runs):
+    import oracle
+    ts = []
+    lab = None
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        lab = oracle.scc_graph(g)
+        ts.append(time.perf_counter() - t0)
+    t = sum(ts) / len(ts)
+    return lab, {"value": g.m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                 "sample": "whole graph, %d run(s) of the sequential Tarjan oracle, mean %.3f s" % (runs, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat_s24_ef16", choices=sorted(WORKLOADS))
+    ap.add_argument("--shrink", type=int, default=0, help="reduce n by 2**shrink (exploration only)")
+    ap.add_argument("--tau", type=int, default=512)
+    ap.add_argument("--cpu-runs", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2303_04934_amd as scc
+
+    cfg, desc = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = graphgen.config(cfg, shrink=args.shrink)
+    print("[bench] generated %s n=%d m=%d in %.1f s" % (args.workload, g.n, g.m, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    dg = scc.to_device(g, "cuda:0")
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    opts = scc.default_options(tau=args.tau, timing=1, validate=0)
+    for _ in range(args.warmup):
+        scc.scc_labels(dg, opts, out=out)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    ms_exp = [0.0, 0.0, 0.0]
+    launches = [0, 0, 0]
+    bexp = [0, 0, 0]
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = scc.scc_labels(dg, opts, return_stats=True, out=out)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    for st in stats:
+        for m in (0, 1, 2):
+            ms_exp[m] += st["ms_kernel"][m]
+            launches[m] += st["launches_kernel"][m]
+            bexp[m] += st["bytes_kernel"][m]
+    got = out.cpu().numpy()
+    print("[bench] timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3), file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC, "value": g.m / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": g.n, "m": g.m, "seed": 1000 + cfg,
+                   "tau": args.tau, "shrink": args.shrink},
+    }
+    dom = max(range(3), key=lambda i: ms_exp[i])
+    if launches[dom] > 0 and ms_exp[dom] > 0:
+        per_launch_ms = ms_exp[dom] / launches[dom]
+        per_launch_bytes = bexp[dom] / launches[dom]
+        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        traffic = load_traffic(args.workload, dom)
+        line["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                            "avg_launch_ms": per_launch_ms, "launches_per_step": launches[dom] / args.steps,
+                            "alg_bytes_per_launch": per_launch_bytes,
+                            "kernel_share_of_step": ms_exp[dom] / args.steps / (dt * 1e3)}
+    last = stats[-1]
+    line["stats"] = {k: last[k] for k in ("ms_trim", "ms_first", "ms_multi", "ms_resize", "ms_label", "batches",
+                                         "rounds_first", "rounds_multi", "dense_rounds", "trimmed", "n_scc",
+                                         "arcs_scanned",
+                                         "claims", "bag_inserts", "table_restarts", "bytes_alg")}
+    line["stats"]["alg_GBps_whole_step"] = last["bytes_alg"] / dt / 1e9
+    line["stats"]["kernel_ms_per_step"] = {KERNEL_SHORT[i]: ms_exp[i] / args.steps for i in range(3)}
+    if not args.no_cpu_baseline:
+        want, cb = cpu_baseline(g, args.cpu_runs)
+        line["cpu_baseline"] = cb
+        ok = bool(np.array_equal(got, want))
+        line["parity"] = "bit-exact vs oracle" if ok else "MISMATCH vs oracle"
+    print(json.dumps(line), flush=True)
+    if line.get("parity", "").startswith("MISMATCH"):
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

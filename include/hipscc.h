@@ -80,7 +80,10 @@ typedef struct {
  *   table_init   reach table slots for the first multi-source batch (power of
  *                two); 0 = the sizing heuristic of Section 4.5.
  *   seeds_per_wave frontier entries a wavefront takes per fetch (1..64);
- *                0 = chosen from the frontier size. */
+ *                0 = chosen from the frontier size.
+ *   timing       1 = bracket every launch of the frontier-expansion kernel
+ *                with HIP events and report its time and algorithmic bytes
+ *                in the stats (costs a little launch overhead). */
 typedef struct {
     int32_t tau;
     float beta;
@@ -95,7 +98,8 @@ typedef struct {
     int32_t trim;
     int64_t table_init;
     int32_t seeds_per_wave;
-    int32_t reserved[7];
+    int32_t timing;
+    int32_t reserved[6];
 } scc_options_t;
 
 /* Per-call statistics (host struct, written when non-NULL).  Times are
@@ -121,8 +125,18 @@ typedef struct {
     int64_t n_scc;            /* number of SCCs (scc_labels only) */
     int64_t policy_calls;     /* rounds decided by the learned policy */
     int64_t policy_fallbacks; /* rounds where the policy output was unusable */
-    int64_t bytes_alg;        /* algorithmic HBM bytes (see DESIGN) */
-    int64_t reserved[8];
+    int64_t bytes_alg;        /* algorithmic HBM bytes of the whole call */
+    /* with options.timing: for the frontier kernels [0] sparse single-source
+     * expand, [1] multi-source expand, [2] dense pull, the summed event time
+     * of their launches, the number of launches and their algorithmic bytes.
+     * Expand: frontier entry 8, offsets 8 per expanded entry, 4 per scanned
+     * arc, 4 per claim attempt, 8 (multi) or 4 (single) per claim, 8 per bag
+     * insert.  Pull: visited and next words (n/4), offsets 8 per unvisited
+     * vertex, 8 per scanned arc (target id + frontier word). */
+    double ms_kernel[3];
+    int64_t launches_kernel[3];
+    int64_t bytes_kernel[3];
+    int64_t reserved[3];
 } scc_stats_t;
 
 /* Library version string (static storage). */

@@ -25,7 +25,7 @@ class Options(ctypes.Structure):
                 ("sigma", ctypes.c_int32), ("kappa", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("policy", ctypes.c_int32), ("dense", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("trim", ctypes.c_int32), ("table_init", ctypes.c_int64),
-                ("seeds_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -35,10 +35,17 @@ class Stats(ctypes.Structure):
                                                "entries_expanded", "arcs_scanned", "claim_attempts", "claims",
                                                "bag_inserts", "bag_chunk_advances", "table_restarts", "trimmed",
                                                "n_scc", "policy_calls", "policy_fallbacks", "bytes_alg")] + \
-               [("reserved", ctypes.c_int64 * 8)]
+               [("ms_kernel", ctypes.c_double * 3), ("launches_kernel", ctypes.c_int64 * 3),
+                ("bytes_kernel", ctypes.c_int64 * 3), ("reserved", ctypes.c_int64 * 3)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d = {}
+        for f, _ in self._fields_:
+            if f == "reserved":
+                continue
+            v = getattr(self, f)
+            d[f] = list(v) if hasattr(v, "__len__") else v
+        return d
 
 
 EXPORTS = ["scc_version", "scc_default_options", "scc_create", "scc_destroy", "scc_last_error", "scc_labels",

@@ -60,11 +60,11 @@ __host__ __device__ __forceinline__ uint64_t bag_chunk_hi(const Bag &B, uint32_t
 // Wave-cooperative Insert.  Every lane of the wave must call it (uniform
 // control flow); lanes with has == true contribute element e.  `wseq` is a
 // per-wave sequence number (wave-uniform) used to draw the random stripe.
-// Returns the number of elements this wave inserted.
+// Returns 1 on the lanes whose element was inserted, else 0.
 __device__ __forceinline__ int bag_insert_wave(const Bag &B, bool has, uint64_t e, uint32_t wave_gid,
                                                uint32_t &wseq) {
     bool pending = has;
-    int inserted = popc64(ballot(has));
+    int inserted = has ? 1 : 0;
     uint64_t mask = ballot(pending);
     while (mask) {
         const int k = popc64(mask);

@@ -6,23 +6,41 @@
 
 namespace hipscc {
 
-// Per-search round control block in device memory.  Rounds alternate between
-// parity 0 and 1 so that one round's counters can be reset while the next
-// round's are in use.
+enum { kCtrSeeds = 0, kCtrExpanded, kCtrArcs, kCtrAttempts, kCtrClaims, kCtrInserts, kNumCtr };
+constexpr int kCtrStripes = 32;
+// counter kinds: expand single-source, expand multi-source, pull, edge-parallel
+enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavy = 3, kNumKinds = 4 };
+
+// Round control of one search lane (one direction of a search), in device
+// memory.  Rounds alternate between parity 0 and 1 so that one round's
+// counters can be reset while the next round's are in use.
 struct RoundCtl {
     uint32_t nF[2];        // frontier sizes
     uint32_t work[2];      // dynamic work counters of the expand kernel
-    uint32_t heavy_n[2];   // entries deferred to the edge-parallel kernel
+    uint32_t heavy_n[2];   // items deferred to the edge-parallel kernel
     uint32_t err;          // kErr* bits
     uint32_t rounds;       // rounds with a non-empty frontier
+    uint32_t listpos;      // bitmap -> list conversion cursor
+    uint32_t pad;
+    unsigned long long fdeg;    // summed degree of the frontier ExtractAll produced
+    unsigned long long claims;  // pairs (or vertices) claimed by this lane's search
+};
+
+// Call-level values shared by all lanes.
+struct Shared {
     uint32_t k;            // sources selected for the batch
-    uint32_t fin;          // vertices finished by the last relabel
+    uint32_t fin;          // vertices finished so far (all batches)
     uint32_t first;        // first active permutation position (batch 1)
     uint32_t emit;         // pairs emitted by scc_reach
     uint32_t nscc;         // canonical representatives
     uint32_t trimmed;
-    uint32_t pad[2];
-    unsigned long long expanded, arcs, attempts, claims, inserts, pairs;
+    uint32_t bad;          // validation flags
+    uint32_t pad;
+};
+
+// Work counters, striped over kCtrStripes slots to spread the atomics.
+struct Counters {
+    unsigned long long c[kCtrStripes][kNumKinds][8];
 };
 
 constexpr uint32_t kErrTable = 1u;      // reach table probe limit exceeded
@@ -32,6 +50,7 @@ constexpr uint32_t kErrUnfinished = 4u; // a vertex had no SCC key at the end
 constexpr int kQcap = 512;  // local queue entries per wave (LDS)
 constexpr int kQmask = kQcap - 1;
 constexpr int kStepArcs = 256;  // arcs a wave commits to per local-search step
+constexpr int kHeavyChunk = 4096;  // arcs per edge-parallel work item
 
 enum { kSingle = 0, kMulti = 1 };
 
@@ -48,14 +67,19 @@ struct Search {
     uint32_t probe_limit;
     const int32_t *srclab;  // kMulti: label of source j
     uint64_t *F;            // packed frontier (read by expand, rewritten by extract)
-    uint64_t *heavy;        // deferred high-degree entries
-    uint64_t fcap;          // capacity of F and heavy
+    uint64_t *heavy;        // deferred high-degree items (entry, chunk) pairs
+    uint64_t fcap;          // capacity of F (entries)
+    uint64_t hcap;          // capacity of heavy (items)
     Bag bag;
     RoundCtl *rc;
+    Counters *cn;
+    int32_t kind;           // counter kind of the expand kernel
     int32_t par;
+    uint32_t fdeg_on;       // ExtractAll also sums the degrees of the new frontier
     int32_t tau;            // <= 1: plain frontier BFS
     int32_t seeds;          // 0: automatic
     int32_t heavy_deg;
+    uint32_t vgc_cut;       // rounds whose frontier has at least this many entries skip local search
 };
 
 // ------------------------------------------------------------- utilities ----
@@ -68,41 +92,85 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
         p[i] = v;
 }
 
-__device__ __forceinline__ void wave_add_u32(uint32_t *ctr, bool pred) {
-    uint64_t m = ballot(pred);
-    if (m && lane_id() == 0) atomicAdd(ctr, (uint32_t)popc64(m));
+// Block-wide sum of per-thread counts, one atomic per block.  Every thread
+// of the block must call it.
+__device__ __forceinline__ void block_add_u32(uint32_t *ctr, uint32_t x) {
+    __shared__ uint32_t part[kWavesPerBlock];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d, kWave);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWavesPerBlock; w++) t += part[w];
+        if (t) atomicAdd(ctr, t);
+    }
+}
+
+// Block-wide flush of the kNumCtr work counters into one stripe.  Returns, on
+// thread i < kNumCtr, the block's total of counter i.
+__device__ __forceinline__ unsigned long long block_flush_ctr(unsigned long long *dst, unsigned long long (&c)[kNumCtr]) {
+    __shared__ unsigned long long part[kWavesPerBlock][kNumCtr];
+#pragma unroll
+    for (int i = 0; i < kNumCtr; i++) c[i] = wave_sum_u64(c[i]);
+    if (lane_id() == 0)
+        for (int i = 0; i < kNumCtr; i++) part[threadIdx.x / kWave][i] = c[i];
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x < kNumCtr) {
+        for (int w = 0; w < kWavesPerBlock; w++) t += part[w][threadIdx.x];
+        if (t) atomicAdd(&dst[threadIdx.x], t);
+    }
+    return t;
 }
 
 // ------------------------------------------------------------------ trim ----
 // Section 4.1: a vertex with zero in- or out-degree is a singleton SCC.
 // Finished vertices store ~key (negative); key = v here.
 __global__ void k_trim(int32_t n, const int32_t *out_off, const int32_t *in_off, int32_t *label, int32_t do_trim,
-                       RoundCtl *rc) {
-    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
-        int64_t v = v0 + threadIdx.x;
-        bool t = false;
-        if (v < n) {
-            t = do_trim && (out_off[v + 1] == out_off[v] || in_off[v + 1] == in_off[v]);
-            label[v] = t ? ~(int32_t)v : 0;
-        }
-        wave_add_u32(&rc->trimmed, t);
+                       Shared *sh) {
+    uint32_t cnt = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool t = do_trim && (out_off[v + 1] == out_off[v] || in_off[v + 1] == in_off[v]);
+        label[v] = t ? ~(int32_t)v : 0;
+        cnt += t;
     }
+    block_add_u32(&sh->trimmed, cnt);
 }
 
 // ----------------------------------------------------- source selection ----
 // Batch 1 of Algorithm 1 is one random vertex; among active vertices, take the
-// first one in permutation order.
-__global__ void k_first_active(Perm P, const int32_t *label, RoundCtl *rc) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < P.n; j += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t v = perm_apply(P, (uint32_t)j);
-        if (label[v] >= 0) atomicMin(&rc->first, (uint32_t)j);
+// first one in permutation order.  Scans positions [p0, p1); one atomic per
+// block after a block-wide minimum.
+__global__ void k_first_active(Perm P, uint32_t p0, uint32_t p1, const int32_t *label, Shared *sh) {
+    __shared__ uint32_t part[kWavesPerBlock];
+    if (p0 > 0 && ld_relaxed(&sh->first) < p0) return;  // an earlier range already found one
+    uint32_t best = 0xffffffffu;
+    for (uint64_t j = p0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < p1; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = perm_apply(P, (uint32_t)j);
+        if (label[v] >= 0) {
+            best = (uint32_t)j;
+            break;  // later positions of this thread are larger
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)best, d, kWave);
+        best = o < best ? o : best;
+    }
+    if (lane_id() == 0) part[threadIdx.x / kWave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = part[0];
+        for (int w = 1; w < kWavesPerBlock; w++) b = part[w] < b ? part[w] : b;
+        if (b != 0xffffffffu) atomicMin(&sh->first, b);
     }
 }
 
 // Sources of one batch: the active vertices among permutation positions
 // [p0, p1) (Algorithm 1: F = P_i intersect V').
 __global__ void k_select_sources(Perm P, uint32_t p0, uint32_t p1, const int32_t *label, int32_t *srcvert,
-                                 int32_t *srclab, RoundCtl *rc) {
+                                 int32_t *srclab, Shared *sh) {
     for (int64_t j0 = p0 + blockIdx.x * (int64_t)blockDim.x; j0 < p1; j0 += (int64_t)gridDim.x * blockDim.x) {
         int64_t j = j0 + threadIdx.x;
         int32_t v = -1, l = -1;
@@ -113,7 +181,7 @@ __global__ void k_select_sources(Perm P, uint32_t p0, uint32_t p1, const int32_t
         bool act = l >= 0;
         uint64_t m = ballot(act);
         uint32_t base = 0;
-        if (m && lane_id() == 0) base = atomicAdd(&rc->k, (uint32_t)popc64(m));
+        if (m && lane_id() == 0) base = atomicAdd(&sh->k, (uint32_t)popc64(m));
         base = wave_bcast_u(base, 0);
         if (act) {
             uint32_t idx = base + rank_below(m);
@@ -159,9 +227,19 @@ __device__ __forceinline__ bool table_contains(const uint64_t *T, uint64_t mask,
     return false;
 }
 
+// The single source of a search: s_fixed if >= 0, else the vertex at the
+// first active permutation position (or -1 when there is none).
+__device__ __forceinline__ int32_t single_source(int32_t s_fixed, const Shared *sh, Perm P) {
+    if (s_fixed >= 0) return s_fixed;
+    const uint32_t j = sh->first;
+    return j < P.n ? (int32_t)perm_apply(P, j) : -1;
+}
+
 // Seed the search: single source.  Bit v of vis = "not available" (outside the
 // subproblem L), plus the source itself, which is claimed up front.
-__global__ void k_premark(int32_t n, const int32_t *label, int32_t L, int32_t s, uint32_t *vis) {
+__global__ void k_premark(int32_t n, const int32_t *label, int32_t L, int32_t s_fixed, const Shared *sh, Perm P,
+                          uint32_t *vis) {
+    const int32_t s = single_source(s_fixed, sh, P);
     for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
         int64_t v = v0 + threadIdx.x;
         bool blocked = v >= n || label[v] != L || v == s;
@@ -174,21 +252,23 @@ __global__ void k_premark(int32_t n, const int32_t *label, int32_t L, int32_t s,
     }
 }
 
-__global__ void k_seed_single(int32_t s, uint64_t *F, RoundCtl *rc) {
+__global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_t *F, RoundCtl *rc) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        F[0] = pair_key(s, 0);
-        rc->nF[0] = 1;
+        const int32_t s = single_source(s_fixed, sh, P);
+        if (s >= 0) F[0] = pair_key(s, 0);
+        rc->nF[0] = s >= 0 ? 1u : 0u;
         rc->nF[1] = 0;
         rc->work[0] = rc->work[1] = 0;
         rc->heavy_n[0] = rc->heavy_n[1] = 0;
         rc->rounds = 0;
+        rc->err = 0;
     }
 }
 
 // Multi-source seed: claim (s_j, j) and put it in the frontier.
-__global__ void k_seed_multi(const int32_t *srcvert, uint64_t *T, uint64_t mask, uint32_t limit, uint64_t *F,
-                             RoundCtl *rc) {
-    const uint32_t k = rc->k;
+__global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, uint64_t *T, uint64_t mask, uint32_t limit,
+                             uint64_t *F, RoundCtl *rc) {
+    const uint32_t k = sh->k;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
         uint64_t key = pair_key(srcvert[j], j);
         if (claim_pair(T, mask, limit, key) < 0) atomicOr(&rc->err, kErrTable);
@@ -234,7 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
     uint32_t nF = ld_relaxed(&rc->nF[S.par]);
     if (nF == 0) return;
     if (nF > S.fcap) nF = (uint32_t)S.fcap;  // overflow was flagged by ExtractAll
-    if (blockIdx.x == 0 && threadIdx.x == 0) rc->rounds += 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rc->rounds += 1;
+        rc->fdeg = 0;
+    }
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + wv;
     uint32_t G = (uint32_t)S.seeds;
@@ -244,15 +327,19 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
         if (G < 1) G = 1;
     }
     const uint32_t ngroups = (nF + G - 1) / G;
-    const bool vgc = S.tau > 1;
+    // Local search exists to give each task enough work when the frontier is
+    // too small to keep the machine busy (Section 3.1); a frontier that
+    // already fills every wavefront runs as a plain round.
+    const bool vgc = S.tau > 1 && nF < S.vgc_cut;
     uint32_t wseq = 0;
-    unsigned long long c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
+    unsigned long long c_seeds = 0, c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
 
     uint32_t grp = wave_gid;
     while (grp < ngroups) {
         const uint32_t start = grp * G;
         const int cnt = (int)((nF - start) < G ? (nF - start) : G);
         if (lane < cnt) Q[lane] = S.F[start + lane];
+        c_seeds += (unsigned long long)cnt;
         int head = 0, tail = cnt;
         long long t = 0;
         const long long budget = vgc ? (long long)S.tau * cnt : 0;
@@ -271,25 +358,43 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
                 d = S.off[u + 1] - beg;
                 if (MODE == kMulti) lab = S.srclab[s];
             }
-            const bool hv = lane < k && d > S.heavy_deg;
-            const int dd = hv ? 0 : d;
-            const int incl = wave_incl_scan(dd);
-            const int excl = incl - dd;
+            // candidate heavy entries (deferred to the edge-parallel kernel)
+            bool hv = lane < k && d > S.heavy_deg;
+            const int nch = hv ? (d + kHeavyChunk - 1) / kHeavyChunk : 0;
             // whole entries whose arcs start within the step's arc window
-            const uint64_t cm = ballot(lane < k && excl < kStepArcs);
+            const int incl0 = wave_incl_scan(hv ? 0 : d);
+            const int excl0 = incl0 - (hv ? 0 : d);
+            const uint64_t cm = ballot(lane < k && excl0 < kStepArcs);
             const int kk = popc64(cm);
             const bool mine = lane < kk;
-            const uint64_t hm = ballot(hv && mine);
-            if (hm) {
+            hv = hv && mine;
+            const int nchm = hv ? nch : 0;
+            const int hincl = wave_incl_scan(nchm);
+            const int htot = wave_bcast(hincl, kWave - 1);
+            if (htot > 0) {
                 uint32_t hb = 0;
-                if (lane == 0) hb = atomicAdd(&rc->heavy_n[S.par], (uint32_t)popc64(hm));
+                if (lane == 0) hb = atomicAdd(&rc->heavy_n[S.par], (uint32_t)htot);
                 hb = wave_bcast_u(hb, 0);
-                if (hv && mine) {
-                    uint64_t pos = (uint64_t)hb + (uint64_t)rank_below(hm);
-                    if (pos < S.fcap) S.heavy[pos] = e;
-                    else atomicOr(&rc->err, kErrCapacity);
+                const bool fits = (uint64_t)hb + (uint64_t)htot <= S.hcap;
+                if (fits) {
+                    for (int c = 0; c < nchm; c++) {
+                        const uint64_t pos = (uint64_t)hb + (uint64_t)(hincl - nchm + c);
+                        S.heavy[2 * pos] = e;
+                        S.heavy[2 * pos + 1] = (uint64_t)c;
+                    }
+                } else {
+                    // no room: blank the reserved items below capacity and
+                    // expand these entries here instead
+                    for (int c = 0; c < nchm; c++) {
+                        const uint64_t pos = (uint64_t)hb + (uint64_t)(hincl - nchm + c);
+                        if (pos < S.hcap) S.heavy[2 * pos] = kEmpty64;
+                    }
+                    hv = false;
                 }
             }
+            const int dd = hv ? 0 : d;
+            const int incl = wave_incl_scan(mine ? dd : 0);
+            const int excl = incl - (mine ? dd : 0);
             const int D = wave_bcast(incl, kk - 1);
             if (mine) {
                 sexcl[lane] = excl;
@@ -350,46 +455,43 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
         if (lane == 0) nxt = atomicAdd(&rc->work[S.par], 1u) + nwaves;
         grp = wave_bcast_u(nxt, 0);
     }
-    c_exp = wave_sum_u64(c_exp);
-    c_arcs = wave_sum_u64(c_arcs);
-    c_att = wave_sum_u64(c_att);
-    c_claims = wave_sum_u64(c_claims);
-    if (lane == 0) {
-        atomicAdd(&rc->expanded, c_exp);
-        atomicAdd(&rc->arcs, c_arcs);
-        atomicAdd(&rc->attempts, c_att);
-        atomicAdd(&rc->claims, c_claims);
-        atomicAdd(&rc->inserts, c_ins);
-    }
+    unsigned long long c[kNumCtr] = {c_seeds, c_exp, c_arcs, c_att, c_claims, c_ins};
+    const unsigned long long t = block_flush_ctr(S.cn->c[blockIdx.x % kCtrStripes][S.kind], c);
+    if (threadIdx.x == kCtrClaims && t) atomicAdd(&rc->claims, t);
 }
 
-// Edge-parallel expansion of the deferred high-degree entries: every wave of
-// the grid takes a 64-arc slice of each list in turn; claims go to the bag.
+// Edge-parallel expansion of the deferred high-degree entries.  Each item is
+// one kHeavyChunk-arc slice of an adjacency list; a block takes an item and
+// its four waves stride over the slice; claims go to the bag.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_expand_heavy(Search S) {
     RoundCtl *rc = S.rc;
     uint32_t nh = ld_relaxed(&rc->heavy_n[S.par]);
     if (nh == 0) return;
-    if (nh > S.fcap) nh = (uint32_t)S.fcap;
+    if (nh > S.hcap) nh = (uint32_t)S.hcap;
     const int lane = lane_id();
-    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int wv = threadIdx.x / kWave;
+    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + wv;
     uint32_t wseq = 0x8000u;
     unsigned long long c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
-    for (uint32_t h = 0; h < nh; h++) {
-        const uint64_t e = S.heavy[h];
+    for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+        const uint64_t e = S.heavy[2 * (uint64_t)h];
+        if (e == kEmpty64) continue;  // block-uniform
+        const uint32_t chunk = (uint32_t)S.heavy[2 * (uint64_t)h + 1];
         const int32_t u = key_vertex(e);
         const uint32_t src = key_source(e);
-        const int32_t beg = S.off[u];
-        const int32_t d = S.off[u + 1] - beg;
+        const int32_t beg0 = S.off[u];
+        const int64_t d = (int64_t)S.off[u + 1] - beg0;
+        const int64_t lo = (int64_t)chunk * kHeavyChunk;
+        const int64_t len = (d - lo) < kHeavyChunk ? (d - lo) : kHeavyChunk;
         const int32_t lab = (MODE == kMulti) ? S.srclab[src] : 0;
-        if (wave_gid == h % nwaves && lane == 0) c_exp++;
-        for (int64_t base = (int64_t)wave_gid * kWave; base < d; base += (int64_t)nwaves * kWave) {
+        if (chunk == 0 && threadIdx.x == 0) c_exp++;
+        for (int64_t base = (int64_t)wv * kWave; base < len; base += kBlock) {
             const int64_t a = base + lane;
             bool claimed = false;
             uint64_t ne = 0;
-            if (a < d) {
-                const int32_t w = S.adj[beg + a];
+            if (a < len) {
+                const int32_t w = S.adj[beg0 + lo + a];
                 c_arcs++;
                 if (MODE == kSingle) {
                     c_att++;
@@ -406,16 +508,113 @@ __global__ __launch_bounds__(kBlock) void k_expand_heavy(Search S) {
             c_ins += (unsigned long long)bag_insert_wave(S.bag, claimed, ne, wave_gid, wseq);
         }
     }
-    c_exp = wave_sum_u64(c_exp);
-    c_arcs = wave_sum_u64(c_arcs);
-    c_att = wave_sum_u64(c_att);
-    c_claims = wave_sum_u64(c_claims);
-    if (lane == 0) {
-        if (c_exp) atomicAdd(&rc->expanded, c_exp);
-        atomicAdd(&rc->arcs, c_arcs);
-        atomicAdd(&rc->attempts, c_att);
-        atomicAdd(&rc->claims, c_claims);
-        atomicAdd(&rc->inserts, c_ins);
+    unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, c_att, c_claims, c_ins};
+    const unsigned long long t = block_flush_ctr(S.cn->c[blockIdx.x % kCtrStripes][kKindHeavy], c);
+    if (threadIdx.x == kCtrClaims && t) atomicAdd(&rc->claims, t);
+}
+
+// ------------------------------------------------------------ dense mode ----
+// Dense round of a single-source search (Section 4.2, the dense-backward
+// optimisation): every vertex of the subproblem that is not yet visited scans
+// its predecessors (in-arcs for a forward search, out-arcs for a backward
+// one) and joins the next frontier at the first predecessor found in the
+// current frontier, skipping its remaining arcs.  A wave owns 64 consecutive
+// vertices, i.e. two bitmap words, so it updates visited/next words with plain
+// stores.  next is written for every word, so it needs no clearing.
+__global__ __launch_bounds__(kBlock) void k_pull(int32_t n, const int32_t *off, const int32_t *adj, uint32_t *vis,
+                                                 const uint32_t *front, uint32_t *next, RoundCtl *rc, Counters *cn,
+                                                 int par) {
+    const int lane = lane_id();
+    uint32_t found_cnt = 0;
+    unsigned long long c_exp = 0, c_arcs = 0;
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); v0 < n;
+         v0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = v0 + lane;
+        const int64_t wi = v >> 5;
+        const uint32_t word = v < n ? vis[wi] : 0xffffffffu;
+        bool found = false;
+        if (v < n && !((word >> (v & 31)) & 1u)) {
+            c_exp++;
+            const int32_t e1 = off[v + 1];
+            for (int32_t e = off[v]; e < e1; e++) {
+                const int32_t u = adj[e];
+                c_arcs++;
+                if ((front[u >> 5] >> (u & 31)) & 1u) {
+                    found = true;
+                    break;
+                }
+            }
+        }
+        const uint64_t m = ballot(found);
+        found_cnt += found ? 1 : 0;
+        if ((lane == 0 || lane == 32) && v < n) {
+            const uint32_t bits = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
+            next[wi] = bits;
+            if (bits) vis[wi] = word | bits;
+        }
+    }
+    block_add_u32(&rc->nF[par ^ 1], found_cnt);
+    unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, 0, 0, 0};
+    block_flush_ctr(cn->c[blockIdx.x % kCtrStripes][kKindPull], c);
+}
+
+__global__ void k_round_end(RoundCtl *rc, int par) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        rc->nF[par] = 0;
+        rc->work[par] = 0;
+        rc->heavy_n[par] = 0;
+        rc->rounds += 1;
+    }
+}
+
+// Frontier list (entries (v, 0)) -> bitmap; bits must be clear on entry.
+__global__ void k_list_to_bitmap(const uint64_t *F, const RoundCtl *rc, int par, uint64_t fcap, uint32_t *bits) {
+    uint64_t nf = rc->nF[par];
+    if (nf > fcap) nf = fcap;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nf; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int32_t v = key_vertex(F[i]);
+        atomicOr(&bits[v >> 5], 1u << (v & 31));
+    }
+}
+
+// Bitmap -> frontier list (order unspecified).  Each block owns a contiguous
+// range of words: it counts their bits, reserves its output range with one
+// atomic, and each thread writes the entries of its own sub-range.
+__global__ __launch_bounds__(kBlock) void k_bitmap_to_list(int32_t n, const uint32_t *bits, uint64_t *F, uint64_t fcap,
+                                                           RoundCtl *rc) {
+    __shared__ uint32_t part[kWavesPerBlock];
+    __shared__ uint32_t base_s;
+    const uint64_t nwords = ((uint64_t)n + 31) >> 5;
+    const uint64_t per_block = (nwords + gridDim.x - 1) / gridDim.x;
+    const uint64_t w0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t w1 = w0 + per_block < nwords ? w0 + per_block : nwords;
+    const uint64_t per_thread = (per_block + kBlock - 1) / kBlock;
+    const uint64_t t0 = w0 + threadIdx.x * per_thread;
+    const uint64_t t1 = t0 + per_thread < w1 ? t0 + per_thread : w1;
+    uint32_t cnt = 0;
+    for (uint64_t w = t0; w < t1; w++) cnt += (uint32_t)__popc(bits[w]);
+    // block exclusive scan of the per-thread counts
+    const int lane = lane_id();
+    int incl = wave_incl_scan((int)cnt);
+    if (lane == kWave - 1) part[threadIdx.x / kWave] = (uint32_t)incl;
+    __syncthreads();
+    uint32_t wave_off = 0, total = 0;
+    for (int w = 0; w < kWavesPerBlock; w++) {
+        if (w < (int)(threadIdx.x / kWave)) wave_off += part[w];
+        total += part[w];
+    }
+    if (threadIdx.x == 0) base_s = total ? atomicAdd(&rc->listpos, total) : 0u;
+    __syncthreads();
+    uint64_t pos = (uint64_t)base_s + wave_off + (uint32_t)(incl - (int)cnt);
+    for (uint64_t w = t0; w < t1; w++) {
+        uint32_t x = bits[w];
+        while (x) {
+            const int b = __ffs(x) - 1;
+            x &= x - 1;
+            const int64_t v = (int64_t)(w << 5) + b;
+            if (v < n && pos < fcap) F[pos] = pair_key((int32_t)v, 0);
+            pos++;
+        }
     }
 }
 
@@ -423,17 +622,24 @@ __global__ __launch_bounds__(kBlock) void k_expand_heavy(Search S) {
 // Packs the bag's used prefix [0, tail[r]) into the frontier array F and
 // clears it (Section 3.3: ExtractAll emits and removes all elements).  A wave
 // handles 64 stripes: a prefix sum of their counts gives each stripe's output
-// offset and one atomic per wave reserves the wave's range.  The last block
-// to finish resets the bag's chunk state and this round's counters.
-__global__ __launch_bounds__(kBlock) void k_bag_extract(Bag B, uint64_t *F, uint64_t fcap, RoundCtl *rc, int par) {
+// offset; a block reserves its four waves' ranges with one atomic.  With
+// S.fdeg_on it also sums the degrees of the extracted entries (the frontier's
+// arc count, used to choose the next round's mode).  The last block to finish
+// resets the bag's chunk state and this round's counters.
+__global__ __launch_bounds__(kBlock) void k_bag_extract(Search S, int par) {
     __shared__ bool last;
+    __shared__ uint32_t part[kWavesPerBlock];
+    __shared__ uint32_t base_s;
+    const Bag &B = S.bag;
+    RoundCtl *rc = S.rc;
     const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
     uint32_t r = ld_relaxed(&B.ctl->r);
     if (r >= B.nchunks) r = B.nchunks - 1;
     const uint64_t nst = bag_chunk_hi(B, r) >> kStripeLog2;
-    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    for (uint64_t sb = (uint64_t)wave_gid * kWave; sb < nst; sb += (uint64_t)nwaves * kWave) {
+    unsigned long long fdeg = 0;
+    for (uint64_t sb0 = (uint64_t)blockIdx.x * kBlock; sb0 < nst; sb0 += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t sb = sb0 + (uint64_t)wv * kWave;
         const uint64_t st = sb + lane;
         uint32_t c = 0;
         if (st < nst) {
@@ -442,10 +648,18 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(Bag B, uint64_t *F, uint
         }
         const int incl = wave_incl_scan((int)c);
         const int tot = wave_bcast(incl, kWave - 1);
+        if (lane == 0) part[wv] = (uint32_t)tot;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) t += part[w];
+            base_s = t ? atomicAdd(&rc->nF[par ^ 1], t) : 0u;
+        }
+        __syncthreads();
+        uint32_t base = base_s;
+        for (int w = 0; w < wv; w++) base += part[w];
+        __syncthreads();  // part/base_s are rewritten next iteration
         if (tot == 0) continue;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&rc->nF[par ^ 1], (uint32_t)tot);
-        base = wave_bcast_u(base, 0);
         const int excl = incl - (int)c;
         for (int j = 0; j < kWave; j++) {
             const int cj = wave_bcast((int)c, j);
@@ -453,11 +667,19 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(Bag B, uint64_t *F, uint
             const uint64_t oj = (uint64_t)base + (uint64_t)wave_bcast(excl, j);
             if (lane < cj) {
                 const uint64_t v = B.slots[((sb + j) << kStripeLog2) + lane];
-                if (oj + lane < fcap) F[oj + lane] = v;
+                if (oj + lane < S.fcap) S.F[oj + lane] = v;
                 else atomicOr(&rc->err, kErrCapacity);
+                if (S.fdeg_on) {
+                    const int32_t u = key_vertex(v);
+                    fdeg += (unsigned long long)(S.off[u + 1] - S.off[u]);
+                }
             }
         }
         if (st < nst && c) B.cnt[st] = 0;
+    }
+    if (S.fdeg_on) {
+        fdeg = wave_sum_u64(fdeg);
+        if (lane == 0 && fdeg) atomicAdd(&rc->fdeg, fdeg);
     }
     // ExtractAll also clears the chunk state: the last block does it once
     // every block has finished reading r.
@@ -484,23 +706,23 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(Bag B, uint64_t *F, uint
 // Single source (the first SCC, Section 4.2): vertices reached both ways are
 // finished with key s; vertices reached one way move to a new subproblem
 // labelled by the hash of (old label, R_in, R_out) (Algorithm 1).
-__global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, int32_t s, const uint32_t *visF,
-                                const uint32_t *visB, RoundCtl *rc) {
-    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = v0 + threadIdx.x;
-        bool fin = false;
-        if (v < n && label[v] == L) {
-            const bool f = (visF[v >> 5] >> (v & 31)) & 1u;
-            const bool b = (visB[v >> 5] >> (v & 31)) & 1u;
-            if (f && b) {
-                label[v] = ~s;
-                fin = true;
-            } else if (f || b) {
-                label[v] = relabel_hash(L, b ? sig_term_in(s) : 0ull, f ? sig_term_out(s) : 0ull);
-            }
+__global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, const Shared *shc, Perm P, const uint32_t *visF,
+                                const uint32_t *visB, Shared *sh) {
+    const int32_t s = single_source(-1, shc, P);
+    if (s < 0) return;
+    uint32_t cnt = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        if (label[v] != L) continue;
+        const bool f = (visF[v >> 5] >> (v & 31)) & 1u;
+        const bool b = (visB[v >> 5] >> (v & 31)) & 1u;
+        if (f && b) {
+            label[v] = ~s;
+            cnt++;
+        } else if (f || b) {
+            label[v] = relabel_hash(L, b ? sig_term_in(s) : 0ull, f ? sig_term_out(s) : 0ull);
         }
-        wave_add_u32(&rc->fin, fin);
     }
+    block_add_u32(&sh->fin, cnt);
 }
 
 // Multi source, pass 1: accumulate the per-vertex set hashes of R_out (pairs
@@ -530,77 +752,88 @@ __global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, const uint64_t
 // table slot is cleared for the next batch.
 __global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, uint64_t min_, const int32_t *srcvert,
                                 unsigned long long *sig_out, unsigned long long *sig_in, int32_t *fin,
-                                int32_t *stamp, int32_t epoch, int32_t *label, RoundCtl *rc) {
+                                int32_t *stamp, int32_t epoch, int32_t *label, Shared *sh) {
     const uint64_t n_out = mout + 1, n_tot = n_out + min_ + 1;
-    for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x; i0 < n_tot; i0 += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t i = i0 + threadIdx.x;
-        bool finished = false;
-        if (i < n_tot) {
-            uint64_t *slot = i < n_out ? Tout + i : Tin + (i - n_out);
-            const uint64_t key = *slot;
-            if (key != kEmpty64) {
-                *slot = kEmpty64;
-                const int32_t v = key_vertex(key);
-                if (atomicExch(&stamp[v], epoch) != epoch) {
-                    const int32_t f = fin[v];
-                    if (f != kInf32) {
-                        label[v] = ~srcvert[f];
-                        finished = true;
-                    } else {
-                        label[v] = relabel_hash(label[v], sig_in[v], sig_out[v]);
-                    }
-                    sig_in[v] = 0;
-                    sig_out[v] = 0;
-                    fin[v] = kInf32;
-                }
-            }
+    uint32_t cnt = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_tot; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t *slot = i < n_out ? Tout + i : Tin + (i - n_out);
+        const uint64_t key = *slot;
+        if (key == kEmpty64) continue;
+        *slot = kEmpty64;
+        const int32_t v = key_vertex(key);
+        if (atomicExch(&stamp[v], epoch) == epoch) continue;
+        const int32_t f = fin[v];
+        if (f != kInf32) {
+            label[v] = ~srcvert[f];
+            cnt++;
+        } else {
+            label[v] = relabel_hash(label[v], sig_in[v], sig_out[v]);
         }
-        wave_add_u32(&rc->fin, finished);
+        sig_in[v] = 0;
+        sig_out[v] = 0;
+        fin[v] = kInf32;
     }
+    block_add_u32(&sh->fin, cnt);
 }
 
 // ---------------------------------------------------------- canonical ----
 // labels_out[v] = min vertex id of v's SCC: every finished vertex holds ~key
 // with key a member of its SCC; a min-reduction per key then a gather.
-__global__ void k_canon_min(int32_t n, const int32_t *label, int32_t *aux, RoundCtl *rc) {
+// aux[k] starts at k: every SCC key is a member of its SCC, so a member v with
+// v >= key cannot lower the minimum.  The rest is first reduced per block in a
+// small LDS hash table (one global atomic per block and key), which keeps the
+// atomics on the key of a giant SCC from serialising.
+__global__ void k_iota(int32_t n, int32_t *a) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        a[v] = (int32_t)v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_canon_min(int32_t n, const int32_t *label, int32_t *aux, uint32_t *err) {
+    constexpr int H = 2 * kBlock;
+    __shared__ int32_t hk[H], hv[H];
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+        hk[i] = -1;
+        hv[i] = kInf32;
+    }
+    __syncthreads();
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t l = label[v];
-        if (l >= 0) {
-            atomicOr(&rc->err, kErrUnfinished);
+        if (l >= 0 || ~l >= n) {
+            atomicOr(err, kErrUnfinished);
             continue;
         }
         const int32_t key = ~l;
-        if (key >= n) {
-            atomicOr(&rc->err, kErrUnfinished);
-            continue;
-        }
-        atomicMin(&aux[key], (int32_t)v);
+        if (v >= key) continue;
+        const int slot = (int)(mix64((uint64_t)key) & (H - 1));
+        const int32_t prev = atomicCAS(&hk[slot], -1, key);
+        if (prev == -1 || prev == key) atomicMin(&hv[slot], (int32_t)v);
+        else atomicMin(&aux[key], (int32_t)v);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < H; i += blockDim.x)
+        if (hk[i] >= 0) atomicMin(&aux[hk[i]], hv[i]);
 }
 
-__global__ void k_canon_write(int32_t n, const int32_t *label, const int32_t *aux, int32_t *out, RoundCtl *rc) {
-    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = v0 + threadIdx.x;
-        bool rep = false;
-        if (v < n) {
-            const int32_t l = label[v];
-            const int32_t r = (l < 0 && ~l < n) ? aux[~l] : -1;
-            out[v] = r;
-            rep = r == v;
-        }
-        wave_add_u32(&rc->nscc, rep);
+__global__ void k_canon_write(int32_t n, const int32_t *label, const int32_t *aux, int32_t *out, Shared *sh) {
+    uint32_t cnt = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t l = label[v];
+        const int32_t r = (l < 0 && ~l < n) ? aux[~l] : -1;
+        out[v] = r;
+        cnt += (r == v);
     }
+    block_add_u32(&sh->nscc, cnt);
 }
 
 // ---------------------------------------------------------- reach output ----
 __global__ void k_emit_single(int32_t n, const int32_t *label, int32_t L, const uint32_t *vis, int32_t s,
-                              int32_t *pairs, uint64_t cap, RoundCtl *rc) {
+                              int32_t *pairs, uint64_t cap, Shared *sh) {
     for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = v0 + threadIdx.x;
         const bool hit = v < n && label[v] == L && ((vis[v >> 5] >> (v & 31)) & 1u);
         const uint64_t m = ballot(hit);
         uint32_t base = 0;
-        if (m && lane_id() == 0) base = atomicAdd(&rc->emit, (uint32_t)popc64(m));
+        if (m && lane_id() == 0) base = atomicAdd(&sh->emit, (uint32_t)popc64(m));
         base = wave_bcast_u(base, 0);
         if (hit) {
             const uint64_t pos = (uint64_t)base + rank_below(m);
@@ -613,7 +846,7 @@ __global__ void k_emit_single(int32_t n, const int32_t *label, int32_t L, const 
     (void)s;
 }
 
-__global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, uint64_t cap, RoundCtl *rc) {
+__global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, uint64_t cap, Shared *sh) {
     const uint64_t nt = mask + 1;
     for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x; i0 < nt; i0 += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t i = i0 + threadIdx.x;
@@ -621,7 +854,7 @@ __global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, u
         const bool hit = key != kEmpty64;
         const uint64_t m = ballot(hit);
         uint32_t base = 0;
-        if (m && lane_id() == 0) base = atomicAdd(&rc->emit, (uint32_t)popc64(m));
+        if (m && lane_id() == 0) base = atomicAdd(&sh->emit, (uint32_t)popc64(m));
         base = wave_bcast_u(base, 0);
         if (hit) {
             const uint64_t pos = (uint64_t)base + rank_below(m);
@@ -636,7 +869,7 @@ __global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, u
 // ------------------------------------------------------------ bag test ----
 // Inserts keys[i] for i with i % rounds == rr, one element per lane.
 __global__ __launch_bounds__(kBlock) void k_bag_insert_test(const uint64_t *keys, int64_t n, int32_t rounds,
-                                                             int32_t rr, Bag B, RoundCtl *rc) {
+                                                             int32_t rr, Bag B, Counters *cn) {
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     uint32_t wseq = 0;
@@ -648,7 +881,8 @@ __global__ __launch_bounds__(kBlock) void k_bag_insert_test(const uint64_t *keys
         const uint64_t e = h ? keys[i * rounds + rr] : 0;
         ins += (unsigned long long)bag_insert_wave(B, h, e, wave_gid, wseq);
     }
-    if (lane_id() == 0 && ins) atomicAdd(&rc->inserts, ins);
+    ins = wave_sum_u64(ins);
+    if (lane_id() == 0 && ins) atomicAdd(&cn->c[blockIdx.x % kCtrStripes][kKindExpandSingle][kCtrInserts], ins);
 }
 
 __global__ void k_copy_u64(const uint64_t *src, uint64_t *dst, const RoundCtl *rc, int par, uint64_t cap) {

@@ -1,19 +1,23 @@
 // hipscc host runtime: the C ABI of include/hipscc.h.
 //
-// Algorithm 1 (BGSS) driven from the host one source batch at a time; each
-// reachability search runs as device-resident rounds (expand -> heavy ->
-// ExtractAll), launched in blocks of rounds between host checks of the
-// frontier size.
+// Algorithm 1 (BGSS) is driven from the host one source batch at a time.  The
+// forward and the backward search of a batch run as two "lanes" whose rounds
+// (expand -> edge-parallel -> ExtractAll, or a dense pull round) are launched
+// interleaved on one stream; the host looks at the frontier sizes only between
+// blocks of rounds.  Everything a batch needs (its source, its sources' count)
+// is resolved on the device, so consecutive batches do not wait for the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hipscc.h"
@@ -24,10 +28,15 @@ using namespace hipscc;
 
 namespace {
 
+// Device control block: the part before `cn` is copied to the host at every
+// check; the counters only when statistics are gathered.
 struct DevCtl {
-    RoundCtl rc;
-    BagCtl bc;
+    RoundCtl lane[2];
+    BagCtl bag[2];
+    Shared sh;
+    Counters cn;
 };
+constexpr size_t kCtlHead = offsetof(DevCtl, cn);
 
 template <typename T>
 struct DevBuf {
@@ -38,6 +47,10 @@ struct DevBuf {
 struct Fail {
     scc_status code;
 };
+
+constexpr int kMaxSlots = 64;   // rounds per launch block
+constexpr int kPhases = 5;      // trim, first, multi, resize, label
+constexpr uint32_t kProbeLimit = 128;
 
 }  // namespace
 
@@ -51,19 +64,29 @@ struct scc_ctx {
 
     DevBuf<int32_t> label, aux, stamp, srcvert, srclab, fin;
     DevBuf<unsigned long long> sig_out, sig_in;
-    DevBuf<uint32_t> visF, visB;
-    DevBuf<uint64_t> Tout, Tin;
-    DevBuf<uint64_t> F, heavy;
-    DevBuf<uint64_t> bag_slots;
-    DevBuf<uint32_t> bag_cnt;
-    uint32_t bag_nchunks = 0;
+    DevBuf<uint32_t> vis[2];        // visited bitmaps of the two single-source lanes
+    DevBuf<uint32_t> bm[2][2];      // front/next bitmaps per lane (dense mode)
+    DevBuf<uint64_t> Tout, Tin;     // reach tables (forward, backward)
+    DevBuf<uint64_t> F[2], heavy[2];
+    DevBuf<uint64_t> bag_slots[2];
+    DevBuf<uint32_t> bag_cnt[2];
+    uint32_t bag_nchunks[2] = {0, 0};
     uint32_t bag_lam_log2 = 0;
     DevCtl *dctl = nullptr;
-    DevCtl *hctl = nullptr;  // pinned
-    DevBuf<int32_t> ubuf;    // batched: union CSR scratch
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    DevCtl *hctl = nullptr;         // pinned
+    DevBuf<int32_t> ubuf;           // batched: union CSR scratch
     uint32_t salt = 1;
-    bool tables_dirty = false;  // a failed call may leave claims behind
+    bool tables_dirty = false;      // a failed call may leave claims behind
+    // options.timing: events around frontier-kernel launches
+    bool timing = false;
+    hipEvent_t tev[2][kMaxSlots][2] = {};
+    double tm_ms[3] = {0, 0, 0};
+    int64_t tm_launches[3] = {0, 0, 0};
+    int64_t dense_rounds = 0;
+    // phase events (statistics)
+    std::vector<hipEvent_t> pev;
+    size_t pev_used = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> plog;
     Policy policy;
 };
 
@@ -145,15 +168,16 @@ void fill_u64(scc_ctx *c, uint64_t *p, uint64_t n, uint64_t v) {
     LAUNCHCHK("k_fill_u64");
 }
 
-void sync_ctl(scc_ctx *c) {
-    HIPCHK(hipMemcpyAsync(c->hctl, c->dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, c->stream));
+// Copies the control head (lanes, bags, shared values) to the host and waits.
+void sync_ctl(scc_ctx *c, bool with_counters = false) {
+    HIPCHK(hipMemcpyAsync(c->hctl, c->dctl, with_counters ? sizeof(DevCtl) : kCtlHead, hipMemcpyDeviceToHost,
+                          c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
 }
 
-void reset_ctl(scc_ctx *c) {
-    // a tiny fill keeps the reset inside the stream (no memset nodes)
-    fill_u32(c, (uint32_t *)c->dctl, sizeof(DevCtl) / 4, 0u);
-}
+// Zeroes the whole control block inside the stream (a fill kernel, no memset).
+void reset_ctl(scc_ctx *c) { fill_u32(c, (uint32_t *)c->dctl, sizeof(DevCtl) / 4, 0u); }
+void reset_lane_ctl(scc_ctx *c, int id) { fill_u32(c, (uint32_t *)&c->dctl->lane[id], sizeof(RoundCtl) / 4, 0u); }
 
 uint64_t next_pow2(uint64_t x) {
     uint64_t p = 1;
@@ -161,9 +185,34 @@ uint64_t next_pow2(uint64_t x) {
     return p;
 }
 
-struct Opts {
-    scc_options_t o;
-};
+// ------------------------------------------------------------- phase log --
+void phase_begin(scc_ctx *c, int phase, bool on) {
+    if (!on) return;
+    if (c->pev_used + 2 > c->pev.size()) {
+        for (int i = 0; i < 64; i++) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            c->pev.push_back(e);
+        }
+    }
+    hipEvent_t a = c->pev[c->pev_used++], b = c->pev[c->pev_used++];
+    HIPCHK(hipEventRecord(a, c->stream));
+    c->plog.push_back({phase, {a, b}});
+}
+void phase_end(scc_ctx *c, bool on) {
+    if (!on || c->plog.empty()) return;
+    HIPCHK(hipEventRecord(c->plog.back().second.second, c->stream));
+}
+// After a final sync: sums the logged phase intervals into ms[kPhases].
+void phase_collect(scc_ctx *c, double *ms) {
+    for (auto &e : c->plog) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e.second.first, e.second.second));
+        ms[e.first] += t;
+    }
+    c->plog.clear();
+    c->pev_used = 0;
+}
 
 scc_options_t defaults() {
     scc_options_t o;
@@ -181,6 +230,7 @@ scc_options_t defaults() {
     o.trim = 1;
     o.table_init = 0;
     o.seeds_per_wave = 0;
+    o.timing = 0;
     return o;
 }
 
@@ -200,410 +250,278 @@ void check_opts(scc_ctx *c, const scc_options_t &o) {
         throw Fail{SCC_EINVAL};
     }
     if (o.policy != 0 && o.policy != 1) { set_err(c, "policy must be 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (o.dense < -1 || o.dense > 1) { set_err(c, "dense must be -1, 0 or 1"); throw Fail{SCC_EINVAL}; }
 }
 
-// Hash bag sized for up to `entries` elements per round: capacity is the
-// smallest lambda * 2^j >= 2 (entries + lambda) (reading of Section 3.3 with
-// alpha = 1/2: the last chunk alone then holds every element).
-void ensure_bag(scc_ctx *c, uint64_t entries, uint32_t lam_log2) {
+// Buffers of lane `id` sized for up to `entries` frontier entries per round.
+// The hash bag's capacity is the smallest lambda * 2^j >= 2 (entries + lambda)
+// (reading of Section 3.3 with alpha = 1/2: the last chunk alone then holds
+// every element).
+void ensure_lane(scc_ctx *c, int id, uint64_t entries, uint32_t lam_log2) {
     const uint64_t lam = 1ull << lam_log2;
     uint32_t nch = 1;
     while ((lam << (nch - 1)) < 2 * (entries + lam)) nch++;
     if (nch > (uint32_t)kMaxChunks) { set_err(c, "hash bag too large"); throw Fail{SCC_ENOMEM}; }
     const uint64_t cap = lam << (nch - 1);
-    bool g1 = false, g2 = false;
-    ensure(c, c->bag_slots, cap, &g1);
-    ensure(c, c->bag_cnt, cap >> kStripeLog2, &g2);
-    if (g2 || lam_log2 != c->bag_lam_log2 || nch > c->bag_nchunks) fill_u32(c, c->bag_cnt.p, c->bag_cnt.cap, 0u);
-    c->bag_nchunks = nch;
+    bool g2 = false;
+    ensure(c, c->bag_slots[id], cap);
+    ensure(c, c->bag_cnt[id], cap >> kStripeLog2, &g2);
+    if (g2 || lam_log2 != c->bag_lam_log2) fill_u32(c, c->bag_cnt[id].p, c->bag_cnt[id].cap, 0u);
+    if (nch > c->bag_nchunks[id] || lam_log2 != c->bag_lam_log2) c->bag_nchunks[id] = nch;
     c->bag_lam_log2 = lam_log2;
-    ensure(c, c->F, entries + kWave);
-    ensure(c, c->heavy, entries + kWave);
+    ensure(c, c->F[id], entries + kWave);
+    ensure(c, c->heavy[id], 2 * (entries + kWave));
 }
 
-Bag make_bag(scc_ctx *c, const scc_options_t &o) {
-    Bag B;
-    B.slots = c->bag_slots.p;
-    B.cnt = c->bag_cnt.p;
-    B.ctl = &c->dctl->bc;
-    B.lam_log2 = c->bag_lam_log2;
-    B.nchunks = c->bag_nchunks;
-    B.sigma = (uint32_t)o.sigma;
-    B.kappa = (uint32_t)o.kappa;
-    B.alpha = o.alpha;
-    B.salt = c->salt;
-    return B;
+// Clears lane id's bag (its stripe counters and chunk state).
+void reset_bag(scc_ctx *c, int id) {
+    fill_u32(c, c->bag_cnt[id].p, c->bag_cnt[id].cap, 0u);
+    fill_u32(c, (uint32_t *)&c->dctl->bag[id], sizeof(BagCtl) / 4, 0u);
 }
 
-// Clears a bag whose state may be inconsistent (after an aborted search).
-void reset_bag(scc_ctx *c) {
-    fill_u32(c, c->bag_cnt.p, c->bag_cnt.cap, 0u);
-    fill_u32(c, (uint32_t *)&c->dctl->bc, sizeof(BagCtl) / 4, 0u);
+Search make_search(scc_ctx *c, int id, const scc_options_t &o, int mode) {
+    Search S;
+    memset(&S, 0, sizeof S);
+    S.F = c->F[id].p;
+    S.heavy = c->heavy[id].p;
+    S.fcap = c->F[id].cap;
+    S.hcap = c->heavy[id].cap / 2;
+    S.bag.slots = c->bag_slots[id].p;
+    S.bag.cnt = c->bag_cnt[id].p;
+    S.bag.ctl = &c->dctl->bag[id];
+    S.bag.lam_log2 = c->bag_lam_log2;
+    S.bag.nchunks = c->bag_nchunks[id];
+    S.bag.sigma = (uint32_t)o.sigma;
+    S.bag.kappa = (uint32_t)o.kappa;
+    S.bag.alpha = o.alpha;
+    S.rc = &c->dctl->lane[id];
+    S.cn = &c->dctl->cn;
+    S.kind = mode == kMulti ? kKindExpandMulti : kKindExpandSingle;
+    S.tau = o.tau;
+    S.seeds = o.seeds_per_wave;
+    S.heavy_deg = 1024;
+    S.probe_limit = kProbeLimit;
+    S.vgc_cut = (uint32_t)c->expand_blocks * kWavesPerBlock;
+    return S;
 }
 
-struct Counters {
-    unsigned long long expanded, arcs, attempts, claims, inserts;
+// ------------------------------------------------------------------ lanes --
+struct Lane {
+    int id = 0;
+    int mode = kSingle;
+    Search S;
+    bool live = false;
+    int par = 0;
+    uint64_t nf = 0;
+    double growth = 1.0;     // frontier growth per round (host estimate)
+    int64_t rounds = 0;
+    // single source
+    bool dense = false, have_list = true;
+    const int32_t *roff = nullptr, *radj = nullptr;
+    int32_t n = 0;
+    // multi source
+    DevBuf<uint64_t> *T = nullptr;
+    uint64_t *tslots = nullptr;
 };
 
-Counters read_counters(const RoundCtl &r) { return {r.expanded, r.arcs, r.attempts, r.claims, r.inserts}; }
+struct DriveParams {
+    const scc_options_t *o = nullptr;
+    int64_t n = 0;           // vertices of the graph
+    int64_t m = 0;           // arcs of the graph
+    int64_t nsub = 0;        // active vertices (upper bound)
+    scc_stats_t *st = nullptr;
+    double *resize_ms = nullptr;
+};
 
-enum SearchResult { kDone = 0, kTableOverflow = 1 };
+// ExtractAll grid: each block walks 256 stripes (16K slots) per step, and the
+// last-block ticket costs one atomic per block, so a modest grid suffices.
+unsigned extract_blocks(scc_ctx *c) { return (unsigned)std::max(c->num_cu / 2, 1); }
 
-// Runs the frontier rounds of one search until the frontier is empty.  The
-// search must already be seeded (frontier in F, nF[0] set).
-// Every round expands entries claimed in the previous round, so a search has
-// at most (claimable entries + 1) rounds; max_rounds guards the host loop.
-template <int MODE>
-SearchResult run_rounds(scc_ctx *c, Search S, int64_t *rounds, uint64_t max_rounds) {
-    int par = 0;
+void launch_sparse(scc_ctx *c, Lane &L, int slot, bool fdeg) {
+    Search &S = L.S;
+    S.par = L.par;
+    S.bag.salt = c->salt++;
+    S.fdeg_on = fdeg ? 1u : 0u;
+    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][slot][0], c->stream));
+    if (L.mode == kMulti) hipLaunchKernelGGL(k_expand<kMulti>, dim3(c->expand_blocks), dim3(kBlock), 0, c->stream, S);
+    else hipLaunchKernelGGL(k_expand<kSingle>, dim3(c->expand_blocks), dim3(kBlock), 0, c->stream, S);
+    LAUNCHCHK("k_expand");
+    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][slot][1], c->stream));
+    if (L.mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, S);
+    else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, S);
+    LAUNCHCHK("k_expand_heavy");
+    hipLaunchKernelGGL(k_bag_extract, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, S, L.par);
+    LAUNCHCHK("k_bag_extract");
+    L.par ^= 1;
+}
+
+void launch_dense(scc_ctx *c, Lane &L) {
+    Search &S = L.S;
+    uint32_t *front = c->bm[L.id][0].p;
+    uint32_t *next = c->bm[L.id][1].p;
+    const uint64_t words = (uint64_t)L.n / 32 + 2;
+    if (L.have_list) {
+        fill_u32(c, front, words, 0u);
+        hipLaunchKernelGGL(k_list_to_bitmap, dim3(grid_for(c, L.nf)), dim3(kBlock), 0, c->stream, S.F, S.rc, L.par,
+                           S.fcap, front);
+        LAUNCHCHK("k_list_to_bitmap");
+        L.have_list = false;
+    }
+    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][0][0], c->stream));
+    hipLaunchKernelGGL(k_pull, dim3(grid_for(c, (uint64_t)L.n)), dim3(kBlock), 0, c->stream, L.n, L.roff, L.radj, S.vis,
+                       front, next, S.rc, S.cn, L.par);
+    LAUNCHCHK("k_pull");
+    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][0][1], c->stream));
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, c->stream, S.rc, L.par);
+    LAUNCHCHK("k_round_end");
+    std::swap(c->bm[L.id][0], c->bm[L.id][1]);
+    L.par ^= 1;
+}
+
+// A multi-source lane whose reach table overflowed restarts on a table twice
+// as large (Section 4.5 resizes once an insertion probes too often; the table
+// cannot grow while claims are in flight).
+void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
+    auto t0 = std::chrono::steady_clock::now();
+    uint64_t &ts = *L.tslots;
+    ts *= 2;
+    bool grew = false;
+    ensure(c, *L.T, ts, &grew);
+    fill_u64(c, L.T->p, grew ? L.T->cap : ts, kEmpty64);
+    ensure_lane(c, L.id, std::max<uint64_t>(ts, (uint64_t)P.n), c->bag_lam_log2);
+    reset_bag(c, L.id);
+    reset_lane_ctl(c, L.id);
+    Search S = make_search(c, L.id, *P.o, kMulti);
+    S.off = L.S.off;
+    S.adj = L.S.adj;
+    S.label = L.S.label;
+    S.srclab = L.S.srclab;
+    S.table = L.T->p;
+    S.tmask = ts - 1;
+    L.S = S;
+    hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)P.n)), dim3(kBlock), 0, c->stream, c->srcvert.p,
+                       &c->dctl->sh, S.table, S.tmask, kProbeLimit, S.F, S.rc);
+    LAUNCHCHK("k_seed_multi");
+    L.par = 0;
+    L.nf = 1;
+    if (P.st) P.st->table_restarts++;
+    if (P.resize_ms) *P.resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Runs seeded lanes until every frontier is empty.
+//
+// Single-source lanes switch between sparse and dense rounds (Section 4.2)
+// by Beamer's rule: dense once the frontier's arcs exceed m / 14, sparse again
+// once the frontier has fewer than nsub / 24 vertices (options.dense forces
+// either mode).  A lane near the switch is checked every round; otherwise
+// rounds go in blocks of K (doubling up to 64) between checks.  Each round
+// expands entries claimed in the previous round, so a search has at most
+// (claimable entries + 1) rounds; the launch count guards the loop.
+void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
+    const int dense_opt = P.o->dense;
+    for (int i = 0; i < nl; i++) {
+        lanes[i].live = true;
+        lanes[i].par = 0;
+        lanes[i].nf = 1;
+        lanes[i].growth = 64.0;
+        lanes[i].dense = dense_opt == 1 && lanes[i].mode == kSingle;
+        lanes[i].have_list = true;
+    }
+    const uint64_t arcs_on = (uint64_t)std::max<int64_t>(P.m / 14, 1);
+    const int64_t back_off = std::max<int64_t>(P.nsub / 24, 1);
     int K = 1;
     uint64_t launched = 0;
-    const unsigned heavy_blocks = (unsigned)c->num_cu * 4;
-    const unsigned extract_blocks = (unsigned)c->num_cu * 2;
+    uint64_t limit = (uint64_t)P.n + 64;
+    for (int i = 0; i < nl; i++)
+        if (lanes[i].mode == kMulti) limit = std::max<uint64_t>(limit, 2 * *lanes[i].tslots + 64);
     for (;;) {
-        for (int i = 0; i < K; i++) {
-            S.par = par;
-            S.bag.salt = c->salt++;
-            hipLaunchKernelGGL(k_expand<MODE>, dim3(c->expand_blocks), dim3(kBlock), 0, c->stream, S);
-            LAUNCHCHK("k_expand");
-            hipLaunchKernelGGL(k_expand_heavy<MODE>, dim3(heavy_blocks), dim3(kBlock), 0, c->stream, S);
-            LAUNCHCHK("k_expand_heavy");
-            hipLaunchKernelGGL(k_bag_extract, dim3(extract_blocks), dim3(kBlock), 0, c->stream, S.bag, S.F, S.fcap,
-                               S.rc, par);
-            LAUNCHCHK("k_bag_extract");
-            par ^= 1;
+        bool any = false, watch = false;
+        for (int i = 0; i < nl; i++) {
+            const Lane &L = lanes[i];
+            if (!L.live) continue;
+            any = true;
+            // watch a lane whose frontier may reach the switch soon: fast
+            // growing frontiers are projected a few rounds ahead
+            const double proj = L.growth >= 2.0 ? std::pow(L.growth, (double)std::min(K, 3)) : 1.0;
+            if (L.mode == kSingle && dense_opt != 0 && (L.dense || (double)L.nf * proj * 16.0 > (double)back_off))
+                watch = true;
         }
-        launched += (uint64_t)K;
+        if (!any) break;
+        const int k = watch ? 1 : K;
+        for (int r = 0; r < k; r++)
+            for (int i = 0; i < nl; i++) {
+                Lane &L = lanes[i];
+                if (!L.live) continue;
+                if (L.dense) {
+                    launch_dense(c, L);
+                    c->dense_rounds++;
+                } else {
+                    launch_sparse(c, L, r, watch && L.mode == kSingle && dense_opt != 0);
+                }
+            }
+        launched += (uint64_t)k;
         sync_ctl(c);
-        const RoundCtl &r = c->hctl->rc;
-        if (r.err & kErrTable) return kTableOverflow;
-        if ((r.err & kErrCapacity) || c->hctl->bc.overflow) {
-            set_err(c, "frontier capacity exceeded (err=%u, bag overflow=%u)", r.err, c->hctl->bc.overflow);
-            throw Fail{SCC_EINTERNAL};
+        bool switched = false;
+        for (int i = 0; i < nl; i++) {
+            Lane &L = lanes[i];
+            if (!L.live) continue;
+            const RoundCtl &rc = c->hctl->lane[L.id];
+            if (c->timing) {
+                const int nslots = L.dense ? 1 : k;
+                const int kind = L.dense ? (int)kKindPull : L.S.kind;
+                for (int s = 0; s < nslots; s++) {
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, c->tev[L.id][s][0], c->tev[L.id][s][1]));
+                    c->tm_ms[kind] += ms;
+                }
+                c->tm_launches[kind] += nslots;
+            }
+            if (L.mode == kMulti && (rc.err & kErrTable)) {
+                restart_multi(c, L, P);
+                continue;
+            }
+            if ((rc.err & kErrCapacity) || c->hctl->bag[L.id].overflow) {
+                set_err(c, "frontier capacity exceeded (err=%u, bag overflow=%u)", rc.err, c->hctl->bag[L.id].overflow);
+                throw Fail{SCC_EINTERNAL};
+            }
+            const uint64_t nf_new = (uint64_t)rc.nF[0] + rc.nF[1];
+            if (L.nf > 0 && nf_new > 0) L.growth = std::pow((double)nf_new / (double)L.nf, 1.0 / (double)(L.dense ? 1 : k));
+            L.nf = nf_new;
+            L.rounds = rc.rounds;
+            if (L.nf == 0) {
+                L.live = false;
+                continue;
+            }
+            L.par = rc.nF[0] ? 0 : 1;
+            if (L.mode != kSingle || dense_opt == 0) continue;
+            if (!L.dense && (dense_opt == 1 || (watch && rc.fdeg > arcs_on))) {
+                L.dense = true;
+                L.have_list = true;
+                switched = true;
+            } else if (L.dense && dense_opt == -1 && (int64_t)L.nf < back_off) {
+                // back to sparse: the bitmap frontier becomes the list F
+                fill_u32(c, &L.S.rc->listpos, 1, 0u);
+                hipLaunchKernelGGL(k_bitmap_to_list, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, L.n,
+                                   c->bm[L.id][0].p, L.S.F, L.S.fcap, L.S.rc);
+                LAUNCHCHK("k_bitmap_to_list");
+                L.dense = false;
+                L.have_list = true;
+                switched = true;
+            }
         }
-        if (r.nF[0] + r.nF[1] == 0) break;
-        if (launched > max_rounds + 64) {
+        if (launched > limit) {
             set_err(c, "internal: search did not finish after %llu rounds", (unsigned long long)launched);
             throw Fail{SCC_EINTERNAL};
         }
-        K = std::min(K * 2, 64);
+        K = switched || watch ? 1 : std::min(K * 2, kMaxSlots);
     }
-    if (rounds) *rounds = c->hctl->rc.rounds;
-    return kDone;
 }
 
+// ------------------------------------------------------------------ graph --
 struct GraphDev {
     int32_t n, m;
     const int32_t *out_off, *out_adj, *in_off, *in_adj;
 };
-
-void validate_graph(scc_ctx *c, const GraphDev &g);
-
-struct PhaseClock {
-    scc_ctx *c;
-    std::chrono::steady_clock::time_point t0;
-    explicit PhaseClock(scc_ctx *cc) : c(cc) {
-        (void)hipStreamSynchronize(c->stream);
-        t0 = std::chrono::steady_clock::now();
-    }
-    double lap() {
-        HIPCHK(hipStreamSynchronize(c->stream));
-        auto t1 = std::chrono::steady_clock::now();
-        double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        t0 = t1;
-        return ms;
-    }
-};
-
-Search base_search(scc_ctx *c, const scc_options_t &o, int tau) {
-    Search S;
-    memset(&S, 0, sizeof S);
-    S.F = c->F.p;
-    S.heavy = c->heavy.p;
-    S.fcap = std::min(c->F.cap, c->heavy.cap);
-    S.bag = make_bag(c, o);
-    S.rc = &c->dctl->rc;
-    S.tau = tau;
-    S.seeds = o.seeds_per_wave;
-    S.heavy_deg = 1024;
-    S.probe_limit = 128;
-    return S;
-}
-
-void add_counters(scc_stats_t *st, const RoundCtl &r) {
-    if (!st) return;
-    st->entries_expanded = (int64_t)r.expanded;
-    st->arcs_scanned = (int64_t)r.arcs;
-    st->claim_attempts = (int64_t)r.attempts;
-    st->claims = (int64_t)r.claims;
-    st->bag_inserts = (int64_t)r.inserts;
-}
-
-// Single-source search from s inside subproblem L (labels), direction dir.
-int64_t single_search(scc_ctx *c, const scc_options_t &o, const GraphDev &g, const int32_t *labels, int dir, int32_t L,
-                      int32_t s, uint32_t *vis, int tau) {
-    const int32_t n = g.n;
-    hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, labels, L, s, vis);
-    LAUNCHCHK("k_premark");
-    hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, s, c->F.p, &c->dctl->rc);
-    LAUNCHCHK("k_seed_single");
-    Search S = base_search(c, o, tau);
-    S.off = dir ? g.in_off : g.out_off;
-    S.adj = dir ? g.in_adj : g.out_adj;
-    S.label = labels;
-    S.vis = vis;
-    int64_t rounds = 0;
-    run_rounds<kSingle>(c, S, &rounds, (uint64_t)n + 1);
-    return rounds;
-}
-
-// Multi-source search of the k sources in srcvert/srclab (rc.k set) into the
-// table T (all EMPTY on entry).  Grows the table and restarts on overflow.
-int64_t multi_search(scc_ctx *c, const scc_options_t &o, const GraphDev &g, const int32_t *labels, int dir,
-                     DevBuf<uint64_t> &T, uint64_t &tslots, int tau, scc_stats_t *st, double *resize_ms) {
-    for (;;) {
-        hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, c->hctl->rc.k)), dim3(kBlock), 0, c->stream, c->srcvert.p,
-                           T.p, tslots - 1, 128u, c->F.p, &c->dctl->rc);
-        LAUNCHCHK("k_seed_multi");
-        Search S = base_search(c, o, tau);
-        S.off = dir ? g.in_off : g.out_off;
-        S.adj = dir ? g.in_adj : g.out_adj;
-        S.label = labels;
-        S.table = T.p;
-        S.tmask = tslots - 1;
-        S.srclab = c->srclab.p;
-        int64_t rounds = 0;
-        if (run_rounds<kMulti>(c, S, &rounds, tslots + 1) == kDone) return rounds;
-        // Section 4.5: resize once an insertion probes too often.  The table
-        // cannot grow while claims are in flight, so the search restarts on a
-        // table twice as large.
-        auto t0 = std::chrono::steady_clock::now();
-        tslots *= 2;
-        bool grew = false;
-        ensure(c, T, tslots, &grew);
-        fill_u64(c, T.p, grew ? T.cap : tslots, kEmpty64);
-        ensure_bag(c, tslots, c->bag_lam_log2);
-        reset_bag(c);
-        // clear the error bit, keep the counters
-        fill_u32(c, &c->dctl->rc.err, 1, 0u);
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (st) st->table_restarts++;
-        if (resize_ms) *resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
-}
-
-void init_call(scc_ctx *c, scc_stats_t *st, int64_t n, int64_t m) {
-    HIPCHK(hipSetDevice(c->device));
-    c->err.clear();
-    if (st) {
-        memset(st, 0, sizeof *st);
-        st->n = n;
-        st->m = m;
-    }
-    if (!c->dctl) {
-        HIPCHK(hipMalloc((void **)&c->dctl, sizeof(DevCtl)));
-        HIPCHK(hipHostMalloc((void **)&c->hctl, sizeof(DevCtl), hipHostMallocDefault));
-    }
-    reset_ctl(c);
-    if (c->tables_dirty) {
-        if (c->Tout.p) fill_u64(c, c->Tout.p, c->Tout.cap, kEmpty64);
-        if (c->Tin.p) fill_u64(c, c->Tin.p, c->Tin.cap, kEmpty64);
-        c->tables_dirty = false;
-    }
-}
-
-void check_graph_args(scc_ctx *c, const scc_graph_t *g) {
-    if (!g) { set_err(c, "graph is NULL"); throw Fail{SCC_EINVAL}; }
-    if (g->n < 0 || g->m < 0) { set_err(c, "negative n or m"); throw Fail{SCC_EINVAL}; }
-    if (!g->out_off || !g->in_off || (g->m > 0 && (!g->out_adj || !g->in_adj))) {
-        set_err(c, "graph has a NULL array");
-        throw Fail{SCC_EINVAL};
-    }
-}
-
-// Per-vertex device state sized for n vertices.
-void ensure_vertex_state(scc_ctx *c, int64_t n) {
-    bool g1, g2, g3;
-    ensure(c, c->label, (uint64_t)n);
-    ensure(c, c->aux, (uint64_t)n);
-    ensure(c, c->stamp, (uint64_t)n, &g1);
-    ensure(c, c->fin, (uint64_t)n, &g2);
-    ensure(c, c->srcvert, (uint64_t)n);
-    ensure(c, c->srclab, (uint64_t)n);
-    ensure(c, c->sig_out, (uint64_t)n, &g3);
-    ensure(c, c->sig_in, (uint64_t)n);
-    ensure(c, c->visF, (uint64_t)n / 32 + 2);
-    ensure(c, c->visB, (uint64_t)n / 32 + 2);
-    (void)g1;
-    (void)g2;
-    (void)g3;
-}
-
-void fill_algbytes(scc_stats_t *st, int64_t n) {
-    if (!st) return;
-    // Algorithmic bytes: offsets per expanded entry (8), target id per scanned
-    // arc (4), target label / visited word per claim attempt (4), table or
-    // bitmap update per claim (8), bag insert + ExtractAll read + frontier
-    // write + frontier read (32 per inserted entry), trim (12 n), canonical
-    // labels (16 n).
-    st->bytes_alg = st->entries_expanded * 8 + st->arcs_scanned * 4 + st->claim_attempts * 4 + st->claims * 8 +
-                    st->bag_inserts * 32 + 28 * n;
-}
-
-void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_options_t &o, scc_stats_t *st) {
-    const int32_t n = g.n;
-    PhaseClock clk(c);
-    if (n == 0) {
-        if (st) st->ms_total = 0;
-        return;
-    }
-    ensure_vertex_state(c, n);
-    if (o.validate) validate_graph(c, g);
-    const int tau = o.tau;
-    // per-call state
-    fill_u32(c, (uint32_t *)c->stamp.p, (uint64_t)n, 0u);
-    fill_u32(c, (uint32_t *)c->fin.p, (uint64_t)n, (uint32_t)kInf32);
-    fill_u64(c, (uint64_t *)c->sig_out.p, (uint64_t)n, 0ull);
-    fill_u64(c, (uint64_t *)c->sig_in.p, (uint64_t)n, 0ull);
-    ensure_bag(c, (uint64_t)n, (uint32_t)o.lambda_log2);
-    reset_bag(c);
-    if (st) st->ms_label += clk.lap();
-
-    // ---- trimming (Section 4.1)
-    hipLaunchKernelGGL(k_trim, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g.out_off, g.in_off,
-                       c->label.p, o.trim ? 1 : 0, &c->dctl->rc);
-    LAUNCHCHK("k_trim");
-    // ---- random permutation (Algorithm 1) and batch 1
-    Perm P;
-    P.n = (uint32_t)n;
-    uint32_t bits = 1;
-    while ((1ull << (2 * bits)) < (uint64_t)n) bits++;
-    P.half_bits = bits;
-    P.key = mix64(o.seed ^ 0x243F6A8885A308D3ull);
-    fill_u32(c, &c->dctl->rc.first, 1, 0xffffffffu);
-    hipLaunchKernelGGL(k_first_active, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, P, c->label.p,
-                       &c->dctl->rc);
-    LAUNCHCHK("k_first_active");
-    sync_ctl(c);
-    int64_t active = (int64_t)n - (int64_t)c->hctl->rc.trimmed;
-    if (st) {
-        st->trimmed = c->hctl->rc.trimmed;
-        st->ms_trim += clk.lap();
-    }
-    uint64_t pos = n;
-    if (active > 0) {
-        const uint32_t j1 = c->hctl->rc.first;
-        if (j1 >= (uint32_t)n) { set_err(c, "no active vertex found"); throw Fail{SCC_EINTERNAL}; }
-        const int32_t s0 = (int32_t)perm_apply(P, j1);
-        // first SCC: single-source searches forward and backward (Section 4.2)
-        int64_t r1 = single_search(c, o, g, c->label.p, 0, 0, s0, c->visF.p, tau);
-        int64_t r2 = single_search(c, o, g, c->label.p, 1, 0, s0, c->visB.p, tau);
-        fill_u32(c, &c->dctl->rc.fin, 1, 0u);
-        if (st) {
-            st->rounds_first = r1 + r2;
-            st->batches = 1;
-            st->ms_first += clk.lap();
-        }
-        hipLaunchKernelGGL(k_finish_single, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p, 0,
-                           s0, c->visF.p, c->visB.p, &c->dctl->rc);
-        LAUNCHCHK("k_finish_single");
-        sync_ctl(c);
-        active -= c->hctl->rc.fin;
-        if (st) st->ms_label += clk.lap();
-        pos = (uint64_t)j1 + 1;
-    }
-    // ---- multi-source batches (Algorithm 1, prefix doubling with beta)
-    double bsize = 1.0;
-    int32_t epoch = 1;
-    uint64_t a_out = 0, a_in = 0;
-    uint64_t ts_out = 0, ts_in = 0;
-    while (active > 0 && pos < (uint64_t)n) {
-        bsize *= (double)o.beta;
-        uint64_t sz = (uint64_t)std::ceil(bsize - 1e-9);
-        uint64_t p1 = std::min<uint64_t>((uint64_t)n, pos + std::max<uint64_t>(sz, 1));
-        fill_u32(c, &c->dctl->rc.k, 1, 0u);
-        hipLaunchKernelGGL(k_select_sources, dim3(grid_for(c, p1 - pos)), dim3(kBlock), 0, c->stream, P, (uint32_t)pos,
-                           (uint32_t)p1, c->label.p, c->srcvert.p, c->srclab.p, &c->dctl->rc);
-        LAUNCHCHK("k_select_sources");
-        sync_ctl(c);
-        pos = p1;
-        const uint32_t k = c->hctl->rc.k;
-        if (k == 0) continue;
-        // Section 4.5: next table size = nextpow2(max(0.3 b, 1.5 a)), b = |V'|,
-        // a = pairs found by the previous search in the same direction.
-        auto size_for = [&](uint64_t a) {
-            uint64_t want = (uint64_t)std::max(0.3 * (double)active, 1.5 * (double)a);
-            want = std::max<uint64_t>(want, 2ull * k);
-            want = std::max<uint64_t>(want, 1024);
-            if (o.table_init > 0 && epoch == 1) want = (uint64_t)o.table_init;
-            return next_pow2(want);
-        };
-        auto t_rs = std::chrono::steady_clock::now();
-        uint64_t want_out = size_for(a_out), want_in = size_for(a_in);
-        bool grew = false;
-        ts_out = want_out;
-        ensure(c, c->Tout, ts_out, &grew);
-        if (grew) fill_u64(c, c->Tout.p, c->Tout.cap, kEmpty64);
-        ts_in = want_in;
-        ensure(c, c->Tin, ts_in, &grew);
-        if (grew) fill_u64(c, c->Tin.p, c->Tin.cap, kEmpty64);
-        c->tables_dirty = true;
-        ensure_bag(c, std::max<uint64_t>(std::max(ts_out, ts_in), (uint64_t)n), c->bag_lam_log2);
-        if (st) st->ms_resize += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_rs).count();
-        (void)clk.lap();
-        const RoundCtl before = c->hctl->rc;
-        double rs = 0;
-        int64_t r1 = multi_search(c, o, g, c->label.p, 0, c->Tout, ts_out, tau, st, &rs);
-        const uint64_t claims_mid = c->hctl->rc.claims;
-        int64_t r2 = multi_search(c, o, g, c->label.p, 1, c->Tin, ts_in, tau, st, &rs);
-        a_out = claims_mid - before.claims + k;
-        a_in = c->hctl->rc.claims - claims_mid + k;
-        if (st) {
-            st->rounds_multi += r1 + r2;
-            st->batches += 1;
-            st->ms_multi += clk.lap() - rs;
-            st->ms_resize += rs;
-        }
-        fill_u32(c, &c->dctl->rc.fin, 1, 0u);
-        const uint64_t tot = ts_out + ts_in;
-        hipLaunchKernelGGL(k_accumulate, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
-                           c->Tin.p, ts_in - 1, 128u, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p);
-        LAUNCHCHK("k_accumulate");
-        hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
-                           c->Tin.p, ts_in - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p, c->stamp.p, epoch,
-                           c->label.p, &c->dctl->rc);
-        LAUNCHCHK("k_relabel_multi");
-        epoch++;
-        sync_ctl(c);
-        active -= c->hctl->rc.fin;
-        if (st) st->ms_label += clk.lap();
-    }
-    if (active != 0) {
-        set_err(c, "internal: %lld vertices left unfinished", (long long)active);
-        throw Fail{SCC_EINTERNAL};
-    }
-    // ---- canonical labels: min vertex id per SCC
-    fill_u32(c, (uint32_t *)c->aux.p, (uint64_t)n, (uint32_t)kInf32);
-    hipLaunchKernelGGL(k_canon_min, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p, c->aux.p,
-                       &c->dctl->rc);
-    LAUNCHCHK("k_canon_min");
-    hipLaunchKernelGGL(k_canon_write, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p,
-                       c->aux.p, labels_out, &c->dctl->rc);
-    LAUNCHCHK("k_canon_write");
-    sync_ctl(c);
-    if (c->hctl->rc.err & kErrUnfinished) {
-        set_err(c, "internal: a vertex ended without an SCC key");
-        throw Fail{SCC_EINTERNAL};
-    }
-    if (st) {
-        st->ms_label += clk.lap();
-        st->n_scc = c->hctl->rc.nscc;
-        add_counters(st, c->hctl->rc);
-        st->ms_total = st->ms_trim + st->ms_first + st->ms_multi + st->ms_resize + st->ms_label;
-        fill_algbytes(st, n);
-    }
-    c->tables_dirty = false;
-}
 
 // O(n + m) checks: offsets start at 0, end at m, never decrease; targets in
 // range; the transposed CSR has the in-degree histogram of the out-arcs.
@@ -628,7 +546,7 @@ __global__ void k_validate_hist(int32_t n, const int32_t *in_off, const int32_t 
 }
 
 void validate_graph(scc_ctx *c, const GraphDev &g) {
-    uint32_t *bad = &c->dctl->rc.pad[0];
+    uint32_t *bad = &c->dctl->sh.bad;
     fill_u32(c, bad, 1, 0u);
     hipLaunchKernelGGL(k_validate_off, dim3(grid_for(c, (uint64_t)g.n + 1)), dim3(kBlock), 0, c->stream, g.n, g.m,
                        g.out_off, bad);
@@ -636,7 +554,7 @@ void validate_graph(scc_ctx *c, const GraphDev &g) {
                        g.in_off, bad);
     LAUNCHCHK("k_validate_off");
     sync_ctl(c);
-    if (c->hctl->rc.pad[0]) {
+    if (c->hctl->sh.bad) {
         set_err(c, "invalid CSR offsets (must start at 0, end at m, never decrease)");
         throw Fail{SCC_EGRAPH};
     }
@@ -647,7 +565,7 @@ void validate_graph(scc_ctx *c, const GraphDev &g) {
                        g.in_adj, (int32_t *)nullptr, bad);
     LAUNCHCHK("k_validate_adj");
     sync_ctl(c);
-    if (c->hctl->rc.pad[0]) {
+    if (c->hctl->sh.bad) {
         set_err(c, "arc target out of range [0, n)");
         throw Fail{SCC_EGRAPH};
     }
@@ -655,11 +573,308 @@ void validate_graph(scc_ctx *c, const GraphDev &g) {
                        c->aux.p, bad);
     LAUNCHCHK("k_validate_hist");
     sync_ctl(c);
-    if (c->hctl->rc.pad[0]) {
+    if (c->hctl->sh.bad) {
         set_err(c, "in-CSR is not the transpose of the out-CSR (in-degree mismatch)");
         throw Fail{SCC_EGRAPH};
     }
-    c->hctl->rc.pad[0] = 0;
+}
+
+// ------------------------------------------------------------ call setup --
+void init_call(scc_ctx *c, scc_stats_t *st, int64_t n, int64_t m, const scc_options_t *o = nullptr) {
+    HIPCHK(hipSetDevice(c->device));
+    c->err.clear();
+    c->timing = o && o->timing;
+    if (c->timing && !c->tev[0][0][0])
+        for (auto &a : c->tev)
+            for (auto &b : a)
+                for (auto &e : b) HIPCHK(hipEventCreate(&e));
+    for (int i = 0; i < 3; i++) {
+        c->tm_ms[i] = 0;
+        c->tm_launches[i] = 0;
+    }
+    c->dense_rounds = 0;
+    c->plog.clear();
+    c->pev_used = 0;
+    if (st) {
+        memset(st, 0, sizeof *st);
+        st->n = n;
+        st->m = m;
+    }
+    reset_ctl(c);
+    if (c->tables_dirty) {
+        if (c->Tout.p) fill_u64(c, c->Tout.p, c->Tout.cap, kEmpty64);
+        if (c->Tin.p) fill_u64(c, c->Tin.p, c->Tin.cap, kEmpty64);
+        c->tables_dirty = false;
+    }
+}
+
+void check_graph_args(scc_ctx *c, const scc_graph_t *g) {
+    if (!g) { set_err(c, "graph is NULL"); throw Fail{SCC_EINVAL}; }
+    if (g->n < 0 || g->m < 0) { set_err(c, "negative n or m"); throw Fail{SCC_EINVAL}; }
+    if (!g->out_off || !g->in_off || (g->m > 0 && (!g->out_adj || !g->in_adj))) {
+        set_err(c, "graph has a NULL array");
+        throw Fail{SCC_EINVAL};
+    }
+}
+
+// Per-vertex device state sized for n vertices.
+void ensure_vertex_state(scc_ctx *c, int64_t n) {
+    ensure(c, c->label, (uint64_t)n);
+    ensure(c, c->aux, (uint64_t)n);
+    ensure(c, c->stamp, (uint64_t)n);
+    ensure(c, c->fin, (uint64_t)n);
+    ensure(c, c->srcvert, (uint64_t)n);
+    ensure(c, c->srclab, (uint64_t)n);
+    ensure(c, c->sig_out, (uint64_t)n);
+    ensure(c, c->sig_in, (uint64_t)n);
+    for (int i = 0; i < 2; i++) {
+        ensure(c, c->vis[i], (uint64_t)n / 32 + 2);
+        ensure(c, c->bm[i][0], (uint64_t)n / 32 + 2);
+        ensure(c, c->bm[i][1], (uint64_t)n / 32 + 2);
+    }
+}
+
+unsigned long long ctr_kind(const Counters &cn, int kind, int i) {
+    unsigned long long t = 0;
+    for (int s = 0; s < kCtrStripes; s++) t += cn.c[s][kind][i];
+    return t;
+}
+
+// Fills the work counters, per-kernel timing and algorithmic bytes (see
+// hipscc.h for the per-event byte counts).  Needs a sync with counters.
+void fill_counters(scc_ctx *c, scc_stats_t *st, int64_t n) {
+    if (!st) return;
+    const Counters &cn = c->hctl->cn;
+    auto sum = [&](int i) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kNumKinds; k++) t += ctr_kind(cn, k, i);
+        return (int64_t)t;
+    };
+    st->entries_expanded = sum(kCtrExpanded);
+    st->arcs_scanned = sum(kCtrArcs);
+    st->claim_attempts = sum(kCtrAttempts);
+    st->claims = sum(kCtrClaims);
+    st->bag_inserts = sum(kCtrInserts);
+    for (int k = 0; k < 3; k++) {
+        st->ms_kernel[k] = c->tm_ms[k];
+        st->launches_kernel[k] = c->tm_launches[k];
+    }
+    for (int k = 0; k < 2; k++)
+        st->bytes_kernel[k] = (int64_t)(ctr_kind(cn, k, kCtrSeeds) * 8 + ctr_kind(cn, k, kCtrExpanded) * 8 +
+                                        ctr_kind(cn, k, kCtrArcs) * 4 + ctr_kind(cn, k, kCtrAttempts) * 4 +
+                                        ctr_kind(cn, k, kCtrClaims) * (k == kKindExpandMulti ? 8 : 4) +
+                                        ctr_kind(cn, k, kCtrInserts) * 8);
+    st->bytes_kernel[2] = (int64_t)(ctr_kind(cn, kKindPull, kCtrExpanded) * 8 + ctr_kind(cn, kKindPull, kCtrArcs) * 8) +
+                          c->dense_rounds * (n / 4);
+    // whole call: searches (expand, edge-parallel, pull), bag traffic
+    // (insert + ExtractAll read + frontier write + frontier read = 32 B per
+    // inserted entry), trimming (12 n) and canonical labels (16 n)
+    st->bytes_alg = st->entries_expanded * 8 + st->arcs_scanned * 4 + st->claim_attempts * 4 + st->claims * 8 +
+                    st->bag_inserts * 32 + 28 * n;
+}
+
+// ------------------------------------------------------------------ SCC --
+void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_options_t &o, scc_stats_t *st) {
+    const int32_t n = g.n;
+    if (n == 0) return;
+    const bool ph = st != nullptr;
+    ensure_vertex_state(c, n);
+    if (o.validate) validate_graph(c, g);
+    // per-call state
+    phase_begin(c, 4, ph);
+    fill_u32(c, (uint32_t *)c->stamp.p, (uint64_t)n, 0u);
+    fill_u32(c, (uint32_t *)c->fin.p, (uint64_t)n, (uint32_t)kInf32);
+    fill_u64(c, (uint64_t *)c->sig_out.p, (uint64_t)n, 0ull);
+    fill_u64(c, (uint64_t *)c->sig_in.p, (uint64_t)n, 0ull);
+    for (int i = 0; i < 2; i++) {
+        ensure_lane(c, i, (uint64_t)n, (uint32_t)o.lambda_log2);
+        reset_bag(c, i);
+    }
+    phase_end(c, ph);
+
+    // ---- trimming (Section 4.1) and the random permutation (Algorithm 1)
+    phase_begin(c, 0, ph);
+    Shared *sh = &c->dctl->sh;
+    hipLaunchKernelGGL(k_trim, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g.out_off, g.in_off,
+                       c->label.p, o.trim ? 1 : 0, sh);
+    LAUNCHCHK("k_trim");
+    Perm P;
+    P.n = (uint32_t)n;
+    uint32_t bits = 1;
+    while ((1ull << (2 * bits)) < (uint64_t)n) bits++;
+    P.half_bits = bits;
+    P.key = mix64(o.seed ^ 0x243F6A8885A308D3ull);
+    // batch 1 is the first active vertex in permutation order: look at a
+    // short prefix first; the scan of the rest returns at once if it found one
+    fill_u32(c, &sh->first, 1, 0xffffffffu);
+    const uint32_t pre = (uint32_t)std::min<int64_t>(n, 65536);
+    hipLaunchKernelGGL(k_first_active, dim3(grid_for(c, pre)), dim3(kBlock), 0, c->stream, P, 0u, pre, c->label.p, sh);
+    LAUNCHCHK("k_first_active");
+    if (pre < (uint32_t)n) {
+        hipLaunchKernelGGL(k_first_active, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, P, pre,
+                           (uint32_t)n, c->label.p, sh);
+        LAUNCHCHK("k_first_active");
+    }
+    phase_end(c, ph);
+
+    // ---- first SCC: forward and backward single-source searches (4.2), as
+    // two lanes.  The source is read on the device.
+    phase_begin(c, 1, ph);
+    Lane L[2];
+    for (int d = 0; d < 2; d++) {
+        hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p, 0, -1,
+                           sh, P, c->vis[d].p);
+        LAUNCHCHK("k_premark");
+        hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, -1, sh, P, c->F[d].p, &c->dctl->lane[d]);
+        LAUNCHCHK("k_seed_single");
+        L[d].id = d;
+        L[d].mode = kSingle;
+        L[d].n = n;
+        L[d].S = make_search(c, d, o, kSingle);
+        L[d].S.off = d ? g.in_off : g.out_off;
+        L[d].S.adj = d ? g.in_adj : g.out_adj;
+        L[d].S.label = c->label.p;
+        L[d].S.vis = c->vis[d].p;
+        L[d].roff = d ? g.out_off : g.in_off;
+        L[d].radj = d ? g.out_adj : g.in_adj;
+    }
+    DriveParams DP;
+    DP.o = &o;
+    DP.n = n;
+    DP.m = g.m;
+    DP.nsub = n;
+    DP.st = st;
+    double resize_ms = 0;
+    DP.resize_ms = &resize_ms;
+    drive(c, L, 2, DP);
+    if (st) st->rounds_first = L[0].rounds + L[1].rounds;
+    phase_end(c, ph);
+    const uint32_t j1 = c->hctl->sh.first;
+    const int64_t trimmed = c->hctl->sh.trimmed;
+    phase_begin(c, 4, ph);
+    hipLaunchKernelGGL(k_finish_single, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p, 0,
+                       sh, P, c->vis[0].p, c->vis[1].p, sh);
+    LAUNCHCHK("k_finish_single");
+    phase_end(c, ph);
+    if (st && j1 < (uint32_t)n) st->batches = 1;
+
+    // ---- multi-source batches (Algorithm 1, prefix doubling with beta).  The
+    // host's view of |V'| lags one batch behind (it is read at the next
+    // check); it is only used as an upper bound.
+    uint64_t pos = j1 < (uint32_t)n ? (uint64_t)j1 + 1 : (uint64_t)n;
+    double bsize = 1.0;
+    int32_t epoch = 1;
+    uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0;
+    int64_t active = (int64_t)n - trimmed;  // upper bound
+    while (active > 0 && pos < (uint64_t)n) {
+        bsize *= (double)o.beta;
+        const uint64_t sz = std::max<uint64_t>((uint64_t)std::ceil(bsize - 1e-9), 1);
+        const uint64_t p1 = std::min<uint64_t>((uint64_t)n, pos + sz);
+        const uint64_t kmax = std::min<uint64_t>(p1 - pos, (uint64_t)active);
+        phase_begin(c, 2, ph);
+        fill_u32(c, &sh->k, 1, 0u);
+        hipLaunchKernelGGL(k_select_sources, dim3(grid_for(c, p1 - pos)), dim3(kBlock), 0, c->stream, P, (uint32_t)pos,
+                           (uint32_t)p1, c->label.p, c->srcvert.p, c->srclab.p, sh);
+        LAUNCHCHK("k_select_sources");
+        pos = p1;
+        // Section 4.5: next table size = nextpow2(max(0.3 b, 1.5 a)), b = |V'|,
+        // a = pairs found by the previous search in the same direction.
+        auto size_for = [&](uint64_t a) {
+            uint64_t want = (uint64_t)std::max(0.3 * (double)active, 1.5 * (double)a);
+            want = std::max<uint64_t>(want, 2 * kmax);
+            want = std::max<uint64_t>(want, 1024);
+            if (o.table_init > 0 && epoch == 1) want = (uint64_t)o.table_init;
+            return next_pow2(want);
+        };
+        auto t_rs = std::chrono::steady_clock::now();
+        ts_out = size_for(a_out);
+        ts_in = size_for(a_in);
+        bool grew = false;
+        ensure(c, c->Tout, ts_out, &grew);
+        if (grew) fill_u64(c, c->Tout.p, c->Tout.cap, kEmpty64);
+        ensure(c, c->Tin, ts_in, &grew);
+        if (grew) fill_u64(c, c->Tin.p, c->Tin.cap, kEmpty64);
+        c->tables_dirty = true;
+        for (int d = 0; d < 2; d++)
+            ensure_lane(c, d, std::max<uint64_t>(d ? ts_in : ts_out, (uint64_t)n), c->bag_lam_log2);
+        resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_rs).count();
+        for (int d = 0; d < 2; d++) {
+            reset_lane_ctl(c, d);
+            DevBuf<uint64_t> &T = d ? c->Tin : c->Tout;
+            uint64_t &ts = d ? ts_in : ts_out;
+            L[d] = Lane();
+            L[d].id = d;
+            L[d].mode = kMulti;
+            L[d].n = n;
+            L[d].T = &T;
+            L[d].tslots = &ts;
+            L[d].S = make_search(c, d, o, kMulti);
+            L[d].S.off = d ? g.in_off : g.out_off;
+            L[d].S.adj = d ? g.in_adj : g.out_adj;
+            L[d].S.label = c->label.p;
+            L[d].S.srclab = c->srclab.p;
+            L[d].S.table = T.p;
+            L[d].S.tmask = ts - 1;
+            hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, kmax)), dim3(kBlock), 0, c->stream, c->srcvert.p, sh, T.p,
+                               ts - 1, kProbeLimit, c->F[d].p, &c->dctl->lane[d]);
+            LAUNCHCHK("k_seed_multi");
+        }
+        DP.nsub = active;
+        drive(c, L, 2, DP);
+        phase_end(c, ph);
+        const uint32_t k = c->hctl->sh.k;
+        a_out = c->hctl->lane[0].claims + k;
+        a_in = c->hctl->lane[1].claims + k;
+        active = (int64_t)n - trimmed - (int64_t)c->hctl->sh.fin;
+        if (k == 0) continue;  // nothing was claimed; the tables are still clean
+        if (st) {
+            st->batches += 1;
+            st->rounds_multi += L[0].rounds + L[1].rounds;
+        }
+        phase_begin(c, 4, ph);
+        const uint64_t tot = ts_out + ts_in;
+        hipLaunchKernelGGL(k_accumulate, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
+                           c->Tin.p, ts_in - 1, kProbeLimit, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p);
+        LAUNCHCHK("k_accumulate");
+        hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
+                           c->Tin.p, ts_in - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p, c->stamp.p, epoch,
+                           c->label.p, sh);
+        LAUNCHCHK("k_relabel_multi");
+        phase_end(c, ph);
+        epoch++;
+    }
+    // ---- canonical labels: min vertex id per SCC
+    phase_begin(c, 4, ph);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->aux.p);
+    LAUNCHCHK("k_iota");
+    hipLaunchKernelGGL(k_canon_min, dim3(grid_for(c, (uint64_t)n, 4)), dim3(kBlock), 0, c->stream, n, c->label.p,
+                       c->aux.p, &sh->bad);
+    LAUNCHCHK("k_canon_min");
+    hipLaunchKernelGGL(k_canon_write, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p,
+                       c->aux.p, labels_out, sh);
+    LAUNCHCHK("k_canon_write");
+    phase_end(c, ph);
+    sync_ctl(c, st != nullptr);
+    if ((c->hctl->sh.bad & kErrUnfinished) ||
+        (int64_t)c->hctl->sh.fin + (int64_t)c->hctl->sh.trimmed != (int64_t)n) {
+        set_err(c, "internal: %lld of %d vertices ended without an SCC key",
+                (long long)((int64_t)n - c->hctl->sh.fin - c->hctl->sh.trimmed), n);
+        throw Fail{SCC_EINTERNAL};
+    }
+    if (st) {
+        double ms[kPhases] = {0, 0, 0, 0, 0};
+        phase_collect(c, ms);
+        st->ms_trim += ms[0];
+        st->ms_first += ms[1];
+        st->ms_multi += ms[2];
+        st->ms_resize += resize_ms;
+        st->ms_label += ms[4];
+        st->trimmed = c->hctl->sh.trimmed;
+        st->n_scc = c->hctl->sh.nscc;
+        st->dense_rounds = c->dense_rounds;
+        fill_counters(c, st, n);
+    }
+    c->tables_dirty = false;
 }
 
 // sources check for scc_reach: in range, label >= 0, distinct (stamp epoch)
@@ -682,7 +897,6 @@ __global__ void k_check_sources(int32_t n, int32_t k, const int32_t *sources, co
 // Union CSR of a batch of graphs: global id = vtx_base[g] + local id.
 __global__ void k_union_off(int32_t G, const int64_t *vb, const int64_t *ab, const int32_t *off_in, int32_t *off_out,
                             int64_t arc0, int32_t g0) {
-    // one thread per global vertex of the group, plus the end offset
     const int64_t v0 = vb[g0];
     const int64_t nv = vb[g0 + G] - v0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= nv; i += (int64_t)gridDim.x * blockDim.x) {
@@ -690,7 +904,7 @@ __global__ void k_union_off(int32_t G, const int64_t *vb, const int64_t *ab, con
             off_out[i] = (int32_t)(ab[g0 + G] - arc0);
             continue;
         }
-        // graph of vertex i: binary search in vb
+        // graph of vertex i: the last graph whose base is <= its global id
         int lo = g0, hi = g0 + G - 1;
         const int64_t gv = v0 + i;
         while (lo < hi) {
@@ -746,11 +960,44 @@ scc_status guard(scc_ctx *c, Fn &&fn) {
     }
 }
 
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void accumulate_stats(scc_stats_t &acc, const scc_stats_t &st) {
+    acc.ms_trim += st.ms_trim;
+    acc.ms_first += st.ms_first;
+    acc.ms_multi += st.ms_multi;
+    acc.ms_resize += st.ms_resize;
+    acc.ms_label += st.ms_label;
+    acc.batches += st.batches;
+    acc.rounds_first += st.rounds_first;
+    acc.rounds_multi += st.rounds_multi;
+    acc.dense_rounds += st.dense_rounds;
+    acc.entries_expanded += st.entries_expanded;
+    acc.arcs_scanned += st.arcs_scanned;
+    acc.claim_attempts += st.claim_attempts;
+    acc.claims += st.claims;
+    acc.bag_inserts += st.bag_inserts;
+    acc.bag_chunk_advances += st.bag_chunk_advances;
+    acc.table_restarts += st.table_restarts;
+    acc.trimmed += st.trimmed;
+    acc.n_scc += st.n_scc;
+    acc.policy_calls += st.policy_calls;
+    acc.policy_fallbacks += st.policy_fallbacks;
+    acc.bytes_alg += st.bytes_alg;
+    for (int k = 0; k < 3; k++) {
+        acc.ms_kernel[k] += st.ms_kernel[k];
+        acc.launches_kernel[k] += st.launches_kernel[k];
+        acc.bytes_kernel[k] += st.bytes_kernel[k];
+    }
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *scc_version(void) { return "hipscc 0.1 (gfx950)"; }
+const char *scc_version(void) { return "hipscc 0.2 (gfx950)"; }
 
 scc_status scc_default_options(scc_options_t *opt) {
     if (!opt) return SCC_EINVAL;
@@ -803,12 +1050,20 @@ void scc_destroy(scc_ctx_t *c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     release(c->label); release(c->aux); release(c->stamp); release(c->srcvert); release(c->srclab);
-    release(c->fin); release(c->sig_out); release(c->sig_in); release(c->visF); release(c->visB);
-    release(c->Tout); release(c->Tin); release(c->F); release(c->heavy); release(c->bag_slots);
-    release(c->bag_cnt); release(c->ubuf);
+    release(c->fin); release(c->sig_out); release(c->sig_in);
+    for (int i = 0; i < 2; i++) {
+        release(c->vis[i]); release(c->bm[i][0]); release(c->bm[i][1]);
+        release(c->F[i]); release(c->heavy[i]); release(c->bag_slots[i]); release(c->bag_cnt[i]);
+    }
+    release(c->Tout); release(c->Tin); release(c->ubuf);
     policy_release(c->policy);
     if (c->dctl) (void)hipFree(c->dctl);
     if (c->hctl) (void)hipHostFree(c->hctl);
+    for (auto &a : c->tev)
+        for (auto &b : a)
+            for (auto &e : b)
+                if (e) (void)hipEventDestroy(e);
+    for (auto e : c->pev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -822,9 +1077,12 @@ scc_status scc_labels(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, c
         if (g->n > 0 && !labels_out) { set_err(c, "labels_out is NULL"); throw Fail{SCC_EINVAL}; }
         scc_options_t o = opt ? *opt : defaults();
         check_opts(c, o);
-        init_call(c, stats, g->n, g->m);
+        const double t0 = now_ms();
+        init_call(c, stats, g->n, g->m, &o);
         GraphDev gd{g->n, g->m, g->out_off, g->out_adj, g->in_off, g->in_adj};
         run_scc(c, gd, labels_out, o, stats);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (stats) stats->ms_total = now_ms() - t0;
     });
 }
 
@@ -842,65 +1100,103 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
         if (capacity > 0 && !pairs_out) { set_err(c, "pairs_out NULL"); throw Fail{SCC_EINVAL}; }
         scc_options_t o = opt ? *opt : defaults();
         check_opts(c, o);
-        init_call(c, stats, g->n, g->m);
+        const double t0 = now_ms();
+        init_call(c, stats, g->n, g->m, &o);
         if (k == 0) return;
         if (k > g->n) { set_err(c, "more sources than vertices"); throw Fail{SCC_EINVAL}; }
+        const int32_t n = g->n;
         GraphDev gd{g->n, g->m, g->out_off, g->out_adj, g->in_off, g->in_adj};
-        ensure_vertex_state(c, g->n);
+        ensure_vertex_state(c, n);
         if (o.validate) validate_graph(c, gd);
-        PhaseClock clk(c);
-        fill_u32(c, (uint32_t *)c->stamp.p, (uint64_t)g->n, 0u);
-        uint32_t *bad = &c->dctl->rc.pad[1];
-        fill_u32(c, bad, 1, 0u);
-        hipLaunchKernelGGL(k_check_sources, dim3(grid_for(c, (uint64_t)k)), dim3(kBlock), 0, c->stream, g->n, k, sources,
-                           labels, c->srcvert.p, c->srclab.p, c->stamp.p, 1, bad);
+        fill_u32(c, (uint32_t *)c->stamp.p, (uint64_t)n, 0u);
+        Shared *sh = &c->dctl->sh;
+        fill_u32(c, &sh->bad, 1, 0u);
+        hipLaunchKernelGGL(k_check_sources, dim3(grid_for(c, (uint64_t)k)), dim3(kBlock), 0, c->stream, n, k, sources,
+                           labels, c->srcvert.p, c->srclab.p, c->stamp.p, 1, &sh->bad);
         LAUNCHCHK("k_check_sources");
-        fill_u32(c, &c->dctl->rc.k, 1, (uint32_t)k);
+        fill_u32(c, &sh->k, 1, (uint32_t)k);
         sync_ctl(c);
-        if (c->hctl->rc.pad[1]) {
-            set_err(c, "sources must be in range, distinct and not excluded (label >= 0); code %u", c->hctl->rc.pad[1]);
+        if (c->hctl->sh.bad) {
+            set_err(c, "sources must be in range, distinct and not excluded (label >= 0); code %u", c->hctl->sh.bad);
             throw Fail{SCC_EINVAL};
         }
-        int64_t rounds = 0;
+        DriveParams DP;
+        DP.o = &o;
+        DP.n = n;
+        DP.m = g->m;
+        DP.nsub = n;
+        DP.st = stats;
+        double rs = 0;
+        DP.resize_ms = &rs;
+        Lane L;
+        L.id = 0;
+        L.n = n;
+        uint64_t ts = 0;
         if (k == 1) {
-            int32_t s = 0, L = 0;
+            int32_t s = 0, lab = 0;
             HIPCHK(hipMemcpyAsync(&s, sources, 4, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            HIPCHK(hipMemcpyAsync(&L, labels + s, 4, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(&lab, labels + s, 4, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            ensure_bag(c, (uint64_t)g->n, (uint32_t)o.lambda_log2);
-            reset_bag(c);
-            rounds = single_search(c, o, gd, labels, dir, L, s, c->visF.p, o.tau);
-            fill_u32(c, &c->dctl->rc.emit, 1, 0u);
-            hipLaunchKernelGGL(k_emit_single, dim3(grid_for(c, (uint64_t)g->n)), dim3(kBlock), 0, c->stream, g->n, labels,
-                               L, c->visF.p, s, pairs_out, (uint64_t)capacity, &c->dctl->rc);
+            ensure_lane(c, 0, (uint64_t)n, (uint32_t)o.lambda_log2);
+            reset_bag(c, 0);
+            Perm P0{(uint32_t)n, 1, 0};
+            hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, labels, lab, s,
+                               sh, P0, c->vis[0].p);
+            hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, s, sh, P0, c->F[0].p, &c->dctl->lane[0]);
+            LAUNCHCHK("k_seed_single");
+            L.mode = kSingle;
+            L.S = make_search(c, 0, o, kSingle);
+            L.S.off = dir ? g->in_off : g->out_off;
+            L.S.adj = dir ? g->in_adj : g->out_adj;
+            L.S.label = labels;
+            L.S.vis = c->vis[0].p;
+            L.roff = dir ? g->out_off : g->in_off;
+            L.radj = dir ? g->out_adj : g->in_adj;
+            drive(c, &L, 1, DP);
+            fill_u32(c, &sh->emit, 1, 0u);
+            hipLaunchKernelGGL(k_emit_single, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, labels, lab,
+                               c->vis[0].p, s, pairs_out, (uint64_t)capacity, sh);
             LAUNCHCHK("k_emit_single");
         } else {
-            uint64_t ts = next_pow2(std::max<uint64_t>(std::max<uint64_t>(1024, 4ull * (uint64_t)k),
-                                                       o.table_init > 0 ? (uint64_t)o.table_init : (uint64_t)g->n / 4));
+            ts = next_pow2(std::max<uint64_t>(std::max<uint64_t>(1024, 4ull * (uint64_t)k),
+                                              o.table_init > 0 ? (uint64_t)o.table_init : (uint64_t)n / 4));
             bool grew = false;
             ensure(c, c->Tout, ts, &grew);
             fill_u64(c, c->Tout.p, grew ? c->Tout.cap : ts, kEmpty64);
             c->tables_dirty = true;
-            ensure_bag(c, std::max<uint64_t>(ts, (uint64_t)g->n), (uint32_t)o.lambda_log2);
-            reset_bag(c);
-            double rs = 0;
-            rounds = multi_search(c, o, gd, labels, dir, c->Tout, ts, o.tau, stats, &rs);
-            fill_u32(c, &c->dctl->rc.emit, 1, 0u);
+            ensure_lane(c, 0, std::max<uint64_t>(ts, (uint64_t)n), (uint32_t)o.lambda_log2);
+            reset_bag(c, 0);
+            hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)k)), dim3(kBlock), 0, c->stream, c->srcvert.p, sh,
+                               c->Tout.p, ts - 1, kProbeLimit, c->F[0].p, &c->dctl->lane[0]);
+            LAUNCHCHK("k_seed_multi");
+            L.mode = kMulti;
+            L.T = &c->Tout;
+            L.tslots = &ts;
+            L.S = make_search(c, 0, o, kMulti);
+            L.S.off = dir ? g->in_off : g->out_off;
+            L.S.adj = dir ? g->in_adj : g->out_adj;
+            L.S.label = labels;
+            L.S.srclab = c->srclab.p;
+            L.S.table = c->Tout.p;
+            L.S.tmask = ts - 1;
+            drive(c, &L, 1, DP);
+            fill_u32(c, &sh->emit, 1, 0u);
             hipLaunchKernelGGL(k_emit_table, dim3(grid_for(c, ts)), dim3(kBlock), 0, c->stream, c->Tout.p, ts - 1,
-                               pairs_out, (uint64_t)capacity, &c->dctl->rc);
+                               pairs_out, (uint64_t)capacity, sh);
             LAUNCHCHK("k_emit_table");
             // leave the table clean for the next call
             fill_u64(c, c->Tout.p, ts, kEmpty64);
-            c->tables_dirty = false;
         }
-        sync_ctl(c);
-        *n_pairs = (int64_t)c->hctl->rc.emit;
+        sync_ctl(c, stats != nullptr);
+        c->tables_dirty = false;
+        *n_pairs = (int64_t)c->hctl->sh.emit;
         if (stats) {
-            stats->ms_total = clk.lap();
-            if (k == 1) stats->rounds_first = rounds; else stats->rounds_multi = rounds;
-            add_counters(stats, c->hctl->rc);
-            fill_algbytes(stats, 0);
+            stats->ms_total = now_ms() - t0;
+            if (k == 1) stats->rounds_first = L.rounds; else stats->rounds_multi = L.rounds;
+            stats->ms_resize = rs;
+            stats->dense_rounds = c->dense_rounds;
+            fill_counters(c, stats, 0);
         }
         if (*n_pairs > capacity) {
             set_err(c, "%lld pairs exceed capacity %lld", (long long)*n_pairs, (long long)capacity);
@@ -920,18 +1216,22 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
         }
         scc_options_t o = opt ? *opt : defaults();
         check_opts(c, o);
-        init_call(c, stats, G ? vtx_base[G] : 0, G ? arc_base[G] : 0);
+        const double t0 = now_ms();
+        init_call(c, stats, G ? vtx_base[G] : 0, G ? arc_base[G] : 0, &o);
         if (G == 0) return;
+        if (vtx_base[0] != 0 || arc_base[0] != 0) {
+            set_err(c, "vtx_base/arc_base must start at 0");
+            throw Fail{SCC_EINVAL};
+        }
         for (int32_t i = 0; i < G; i++) {
-            if (vtx_base[i + 1] < vtx_base[i] || arc_base[i + 1] < arc_base[i] || vtx_base[0] != 0 || arc_base[0] != 0) {
-                set_err(c, "vtx_base/arc_base must start at 0 and never decrease");
+            if (vtx_base[i + 1] < vtx_base[i] || arc_base[i + 1] < arc_base[i]) {
+                set_err(c, "vtx_base/arc_base must never decrease");
                 throw Fail{SCC_EINVAL};
             }
             if (arc_base[i + 1] - arc_base[i] >= (1ll << 31)) { set_err(c, "graph %d has >= 2^31 arcs", i); throw Fail{SCC_EINVAL}; }
         }
         if (vtx_base[G] >= (1ll << 31)) { set_err(c, "total vertex count must be < 2^31"); throw Fail{SCC_EINVAL}; }
         if (arc_base[G] > 0 && (!out_adj || !in_adj)) { set_err(c, "adjacency NULL"); throw Fail{SCC_EINVAL}; }
-        // device copies of the bases
         DevBuf<int64_t> dvb, dab;
         struct Free {
             DevBuf<int64_t> &a, &b;
@@ -941,7 +1241,8 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
         ensure(c, dab, (uint64_t)G + 1);
         HIPCHK(hipMemcpyAsync(dvb.p, vtx_base, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(dab.p, arc_base, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, c->stream));
-        // groups of consecutive graphs whose union has < 2^31 arcs
+        // groups of consecutive graphs whose union has < 2^31 arcs; the
+        // disjoint union of a group is one digraph whose SCCs are the graphs'
         scc_stats_t acc;
         memset(&acc, 0, sizeof acc);
         int32_t g0 = 0;
@@ -968,29 +1269,19 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
             LAUNCHCHK("k_union_*");
             GraphDev gd{(int32_t)nv, (int32_t)na, uo, ua, ui, uia};
             scc_stats_t st;
-            memset(&st, 0, sizeof st);
-            reset_ctl(c);
+            init_call(c, stats ? &st : nullptr, nv, na, &o);
             run_scc(c, gd, ul, o, stats ? &st : nullptr);
             hipLaunchKernelGGL(k_union_labels, dim3(grid_for(c, (uint64_t)nv)), dim3(kBlock), 0, c->stream, cnt, dvb.p, ul,
                                labels_out, g0);
             LAUNCHCHK("k_union_labels");
             HIPCHK(hipStreamSynchronize(c->stream));
-            if (stats) {
-                acc.ms_total += st.ms_total; acc.ms_trim += st.ms_trim; acc.ms_first += st.ms_first;
-                acc.ms_multi += st.ms_multi; acc.ms_resize += st.ms_resize; acc.ms_label += st.ms_label;
-                acc.batches += st.batches; acc.rounds_first += st.rounds_first; acc.rounds_multi += st.rounds_multi;
-                acc.dense_rounds += st.dense_rounds; acc.entries_expanded += st.entries_expanded;
-                acc.arcs_scanned += st.arcs_scanned; acc.claim_attempts += st.claim_attempts; acc.claims += st.claims;
-                acc.bag_inserts += st.bag_inserts; acc.bag_chunk_advances += st.bag_chunk_advances;
-                acc.table_restarts += st.table_restarts; acc.trimmed += st.trimmed; acc.n_scc += st.n_scc;
-                acc.policy_calls += st.policy_calls; acc.policy_fallbacks += st.policy_fallbacks;
-                acc.bytes_alg += st.bytes_alg;
-            }
+            if (stats) accumulate_stats(acc, st);
             g0 = g1;
         }
         if (stats) {
             acc.n = vtx_base[G];
             acc.m = arc_base[G];
+            acc.ms_total = now_ms() - t0;
             *stats = acc;
         }
     });
@@ -1027,34 +1318,35 @@ scc_status scc_bag_selftest(scc_ctx_t *c, const uint64_t *keys, int64_t n, int32
         *n_out = 0;
         scc_options_t o = opt ? *opt : defaults();
         check_opts(c, o);
-        init_call(c, stats, n, 0);
+        init_call(c, stats, n, 0, &o);
         const uint64_t per_round = (uint64_t)((n + rounds - 1) / rounds);
-        ensure_bag(c, std::max<uint64_t>(per_round, 1), (uint32_t)o.lambda_log2);
-        ensure(c, c->F, (uint64_t)n + kWave);
-        reset_bag(c);
-        Bag B = make_bag(c, o);
+        ensure_lane(c, 0, std::max<uint64_t>(per_round, 1), (uint32_t)o.lambda_log2);
+        ensure(c, c->F[0], (uint64_t)n + kWave);
+        reset_bag(c, 0);
+        Search S = make_search(c, 0, o, kSingle);
         uint64_t adv = 0;
         for (int32_t rr = 0; rr < rounds; rr++) {
-            B.salt = c->salt++;
+            S.bag.salt = c->salt++;
             hipLaunchKernelGGL(k_bag_insert_test, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, keys, n,
-                               rounds, rr, B, &c->dctl->rc);
+                               rounds, rr, S.bag, S.cn);
             LAUNCHCHK("k_bag_insert_test");
             sync_ctl(c);
-            adv += c->hctl->bc.advances;
-            if (c->hctl->bc.overflow) { set_err(c, "bag overflow"); throw Fail{SCC_EINTERNAL}; }
+            adv += c->hctl->bag[0].advances;
+            if (c->hctl->bag[0].overflow) { set_err(c, "bag overflow"); throw Fail{SCC_EINTERNAL}; }
             // par = 1: ExtractAll appends to nF[0], which accumulates over rounds
-            hipLaunchKernelGGL(k_bag_extract, dim3((unsigned)c->num_cu * 2), dim3(kBlock), 0, c->stream, B, c->F.p,
-                               (uint64_t)c->F.cap, &c->dctl->rc, 1);
+            hipLaunchKernelGGL(k_bag_extract, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, S, 1);
             LAUNCHCHK("k_bag_extract");
-            fill_u32(c, &c->dctl->bc.advances, 1, 0u);
+            fill_u32(c, &c->dctl->bag[0].advances, 1, 0u);
         }
-        sync_ctl(c);
-        const uint64_t got = c->hctl->rc.nF[0];
-        if (got > 0) HIPCHK(hipMemcpyAsync(out, c->F.p, 8 * std::min<uint64_t>(got, (uint64_t)n), hipMemcpyDeviceToDevice, c->stream));
+        sync_ctl(c, true);
+        const uint64_t got = c->hctl->lane[0].nF[0];
+        if (got > 0)
+            HIPCHK(hipMemcpyAsync(out, c->F[0].p, 8 * std::min<uint64_t>(got, (uint64_t)n), hipMemcpyDeviceToDevice,
+                                  c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         *n_out = (int64_t)got;
         if (stats) {
-            stats->bag_inserts = (int64_t)c->hctl->rc.inserts;
+            stats->bag_inserts = (int64_t)ctr_kind(c->hctl->cn, kKindExpandSingle, kCtrInserts);
             stats->bag_chunk_advances = (int64_t)adv;
         }
     });

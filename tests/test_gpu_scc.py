@@ -204,3 +204,28 @@ def test_policy_kernel_matches_cpu_forward(gpu):
     bad[7] = np.nan
     with pytest.raises(gpu.SccError):
         gpu.policy_load(bad)
+
+
+@pytest.mark.parametrize("dense", [-1, 0, 1])
+def test_dense_mode_invariance(gpu, dense):
+    for g in (graphgen.rmat(13, 16, seed=11), graphgen.torus(80, 80, 0.6, seed=12),
+              graphgen.knn(30000, 3, 5, 0.01, seed=13)):
+        st = check_labels(gpu, g, gpu.default_options(dense=dense), name="%s dense=%d" % (g.name, dense))
+        if dense == 1:
+            assert st["dense_rounds"] > 0
+        if dense == 0:
+            assert st["dense_rounds"] == 0
+
+
+def test_dense_reach_matches_oracle(gpu):
+    g = graphgen.rmat(12, 16, seed=14)
+    dg = gpu.to_device(g)
+    lab = np.zeros(g.n, np.int32)
+    for dense in (1, -1):
+        for d in (0, 1):
+            say("dense reach", dense, d)
+            got = gpu.scc_reach(dg, [int(np.argmax(np.diff(g.out_off)))], lab, direction=d,
+                                options=gpu.default_options(dense=dense)).cpu().numpy()
+            off, adj = (g.out_off, g.out_adj) if d == 0 else (g.in_off, g.in_adj)
+            want = oracle.reach_pairs(g.n, off, adj, lab, [int(np.argmax(np.diff(g.out_off)))])
+            assert np.array_equal(sorted_pairs(got), want)
