@@ -72,7 +72,9 @@ typedef struct {
  *   alpha        target load factor of a bag chunk (0 < alpha < 1).
  *   seed         seed of the random vertex permutation.
  *   policy       0 = fixed schedule, 1 = learned per-round policy (needs
- *                scc_policy_load; falls back to the fixed schedule otherwise).
+ *                scc_policy_load; falls back to the fixed schedule otherwise),
+ *                2 = exploration: a random budget class per round (for
+ *                collecting training traces).
  *   dense        single-source search direction mode: -1 automatic,
  *                0 never pull, 1 always pull (Section 4.2).
  *   validate     1 = check the CSR (O(n + m)) before running.
@@ -83,7 +85,9 @@ typedef struct {
  *                0 = chosen from the frontier size.
  *   timing       1 = bracket every launch of the frontier-expansion kernel
  *                with HIP events and report its time and algorithmic bytes
- *                in the stats (costs a little launch overhead). */
+ *                in the stats (costs a little launch overhead).
+ *   trace        1 = record one row per search round (read back with
+ *                scc_trace_read); the host then checks every round. */
 typedef struct {
     int32_t tau;
     float beta;
@@ -99,7 +103,8 @@ typedef struct {
     int64_t table_init;
     int32_t seeds_per_wave;
     int32_t timing;
-    int32_t reserved[6];
+    int32_t trace;
+    int32_t reserved[5];
 } scc_options_t;
 
 /* Per-call statistics (host struct, written when non-NULL).  Times are
@@ -201,6 +206,19 @@ scc_status scc_policy_load(scc_ctx_t *ctx, const float *weights, int64_t n_float
  * device inference kernel; writes float32[rows*8] scores to host `scores`.
  * Test hook for parity with a CPU forward pass. */
 scc_status scc_policy_eval(scc_ctx_t *ctx, const float *feats, int32_t rows, float *scores);
+
+/* Per-round trace of the last call made with options.trace = 1: one row of
+ * SCC_TRACE_FIELDS floats per round and search lane:
+ *   0 kind (0 single-source sparse, 1 single-source dense, 2 multi-source)
+ *   1..5 the policy features before the round (log2(1 + frontier size),
+ *        log2(1 + frontier degree sum), visited fraction, log2(1 + round),
+ *        log2(1 + deepest local search of the previous round))
+ *   6 VGC budget used, 7 round time in ms (events), 8 entries claimed in
+ *   the round, 9 frontier size after the round, 10 batch index, 11 n.
+ * out: host float[cap * SCC_TRACE_FIELDS]; *n_rows receives the row count
+ * (rows beyond cap are dropped). */
+#define SCC_TRACE_FIELDS 12
+scc_status scc_trace_read(scc_ctx_t *ctx, float *out, int64_t cap, int64_t *n_rows);
 
 /* Hash bag self test (Section 3.3).  keys: device uint64[n] (any values);
  * every key is inserted by a concurrent wave-aggregated Insert in `rounds`

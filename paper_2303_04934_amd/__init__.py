@@ -20,7 +20,10 @@ from . import _native
 from ._native import POLICY_FLOATS, STATUS_NAMES, Options, Stats
 
 __all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_reach",
-           "scc_labels_batched", "bag_selftest", "policy_load", "policy_eval", "version", "POLICY_FLOATS"]
+           "scc_labels_batched", "bag_selftest", "policy_load", "policy_eval", "trace_read", "version",
+           "POLICY_FLOATS", "TRACE_FIELDS"]
+
+TRACE_FIELDS = _native.TRACE_FIELDS
 
 
 class SccError(RuntimeError):
@@ -179,6 +182,19 @@ def bag_selftest(keys, rounds: int = 1, options: Options | None = None, return_s
     _check(lib, ctx, rc)
     out = out[:cnt.value]
     return (out, st.as_dict()) if return_stats else out
+
+
+def trace_read(device_index: int = 0):
+    """Per-round trace rows of the last call made with options.trace=1 on the
+    current stream's context, as a float32 array [rows, TRACE_FIELDS]."""
+    torch = _torch()
+    lib = _native.load()
+    ctx = _ctx(device_index, torch.cuda.current_stream(device_index).cuda_stream)
+    n = ctypes.c_int64(0)
+    _check(lib, ctx, lib.scc_trace_read(ctx, None, 0, ctypes.byref(n)))
+    out = np.empty((max(int(n.value), 1), TRACE_FIELDS), np.float32)
+    _check(lib, ctx, lib.scc_trace_read(ctx, out.ctypes.data, int(n.value), ctypes.byref(n)))
+    return out[:int(n.value)]
 
 
 def policy_load(weights, device_index: int = 0):

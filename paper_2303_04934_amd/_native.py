@@ -25,7 +25,8 @@ class Options(ctypes.Structure):
                 ("sigma", ctypes.c_int32), ("kappa", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("policy", ctypes.c_int32), ("dense", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("trim", ctypes.c_int32), ("table_init", ctypes.c_int64),
-                ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -49,7 +50,9 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["scc_version", "scc_default_options", "scc_create", "scc_destroy", "scc_last_error", "scc_labels",
-           "scc_reach", "scc_labels_batched", "scc_policy_load", "scc_policy_eval", "scc_bag_selftest"]
+           "scc_reach", "scc_labels_batched", "scc_policy_load", "scc_policy_eval", "scc_bag_selftest",
+           "scc_trace_read"]
+TRACE_FIELDS = 12
 
 _lib = None
 
@@ -77,6 +80,7 @@ def load():
     lib.scc_policy_load.argtypes = [vp, vp, i64]
     lib.scc_policy_eval.argtypes = [vp, vp, i32, vp]
     lib.scc_bag_selftest.argtypes = [vp, vp, i64, i32, vp, P(i64), P(Options), P(Stats)]
+    lib.scc_trace_read.argtypes = [vp, vp, i64, P(i64)]
     for name in EXPORTS:
         if name not in ("scc_version", "scc_destroy", "scc_last_error"):
             getattr(lib, name).restype = ctypes.c_int32

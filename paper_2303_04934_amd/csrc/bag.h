@@ -57,18 +57,34 @@ __host__ __device__ __forceinline__ uint64_t bag_chunk_hi(const Bag &B, uint32_t
     return 1ull << (B.lam_log2 + i);
 }
 
-// Wave-cooperative Insert.  Every lane of the wave must call it (uniform
-// control flow); lanes with has == true contribute element e.  `wseq` is a
-// per-wave sequence number (wave-uniform) used to draw the random stripe.
-// Returns 1 on the lanes whose element was inserted, else 0.
-__device__ __forceinline__ int bag_insert_wave(const Bag &B, bool has, uint64_t e, uint32_t wave_gid,
-                                               uint32_t &wseq) {
-    bool pending = has;
-    int inserted = has ? 1 : 0;
-    uint64_t mask = ballot(pending);
-    while (mask) {
-        const int k = popc64(mask);
-        const int my = rank_below(mask);
+// Wave-cooperative Insert of up to A elements per lane.  Every lane of the
+// wave must call it (uniform control flow); element j of a lane is present
+// when has[j].  The wave's elements are ranked (slot j, then lane) and
+// reserved together: one fetch-and-add on a random stripe of chunk r claims
+// room for all of them, the remainder spills to the next stripe (the probe).
+// `wseq` is a per-wave sequence number (wave-uniform) used to draw the stripe.
+// Returns the number of this lane's elements that were inserted.
+template <int A>
+__device__ __forceinline__ int bag_insert_wave_n(const Bag &B, const bool (&has)[A], const uint64_t (&e)[A],
+                                                 uint32_t wave_gid, uint32_t &wseq) {
+    bool pending[A];
+    int inserted = 0;
+#pragma unroll
+    for (int j = 0; j < A; j++) {
+        pending[j] = has[j];
+        inserted += has[j] ? 1 : 0;
+    }
+    for (;;) {
+        // rank of each pending element in (slot, lane) order
+        int my[A];
+        int k = 0;
+#pragma unroll
+        for (int j = 0; j < A; j++) {
+            const uint64_t m = ballot(pending[j]);
+            my[j] = k + rank_below(m);
+            k += popc64(m);
+        }
+        if (k == 0) break;
         uint32_t r = ld_relaxed(&B.ctl->r);
         if (r >= B.nchunks) r = B.nchunks - 1;
         const bool last = (r + 1 >= B.nchunks);
@@ -77,14 +93,18 @@ __device__ __forceinline__ int bag_insert_wave(const Bag &B, bool has, uint64_t 
         // Sampling (Section 3.3): rate sigma / (alpha * size).
         bool advanced = false;
         if (!last) {
-            double rate = (double)B.sigma / ((double)B.alpha * (double)size);
-            uint32_t thr = rate >= 1.0 ? 0xffffffffu : (uint32_t)(rate * 4294967296.0);
-            uint32_t coin = (uint32_t)mix64(e ^ ((uint64_t)B.salt << 32) ^ 0x5851F42D4C957F2Dull);
-            const int ns = popc64(ballot(pending && coin < thr));
+            const double rate = (double)B.sigma / ((double)B.alpha * (double)size);
+            const uint32_t thr = rate >= 1.0 ? 0xffffffffu : (uint32_t)(rate * 4294967296.0);
+            int ns = 0;
+#pragma unroll
+            for (int j = 0; j < A; j++) {
+                const uint32_t coin = (uint32_t)mix64(e[j] ^ ((uint64_t)B.salt << 32) ^ 0x5851F42D4C957F2Dull);
+                ns += popc64(ballot(pending[j] && coin < thr));
+            }
             if (ns > 0) {
                 uint32_t adv = 0;
                 if (lane_id() == 0) {
-                    uint32_t old = atomicAdd(&B.ctl->sample[r], (uint32_t)ns);
+                    const uint32_t old = atomicAdd(&B.ctl->sample[r], (uint32_t)ns);
                     if (old + (uint32_t)ns >= B.sigma) {
                         // try_resize: only one CAS from r wins
                         if (atomicCAS(&B.ctl->r, r, r + 1) == r) atomicAdd(&B.ctl->advances, 1u);
@@ -94,26 +114,23 @@ __device__ __forceinline__ int bag_insert_wave(const Bag &B, bool has, uint64_t 
                 advanced = wave_bcast_u(adv, 0) != 0;
             }
         }
-        if (advanced) {
-            mask = ballot(pending);
-            continue;  // insert again into the new chunk
-        }
+        if (advanced) continue;  // insert again into the new chunk
         const uint32_t nst = (uint32_t)(size >> kStripeLog2);
         const uint32_t st0 = (uint32_t)(lo >> kStripeLog2);
-        uint32_t st = (uint32_t)(mix64(((uint64_t)wave_gid << 32) ^ (uint64_t)(wseq++) ^
-                                       ((uint64_t)B.salt << 20)) % nst);
+        uint32_t st = (uint32_t)(mix64(((uint64_t)wave_gid << 32) ^ (uint64_t)(wseq++) ^ ((uint64_t)B.salt << 20)) % nst);
         int placed = 0;
         uint32_t probes = 0;
-        bool spill = false;
+        bool spill = false, lost = false;
         while (placed < k) {
             uint32_t o = 0;
             if (lane_id() == 0) o = atomicAdd(&B.cnt[st0 + st], (uint32_t)(k - placed));
             o = wave_bcast_u(o, 0);
             int avail = o < (uint32_t)kStripe ? (int)((uint32_t)kStripe - o) : 0;
             if (avail > k - placed) avail = k - placed;
-            if (pending && my >= placed && my < placed + avail) {
-                B.slots[((uint64_t)(st0 + st) << kStripeLog2) + o + (uint32_t)(my - placed)] = e;
-            }
+#pragma unroll
+            for (int j = 0; j < A; j++)
+                if (pending[j] && my[j] >= placed && my[j] < placed + avail)
+                    B.slots[((uint64_t)(st0 + st) << kStripeLog2) + o + (uint32_t)(my[j] - placed)] = e[j];
             placed += avail;
             if (placed < k) {
                 st = (st + 1 == nst) ? 0 : st + 1;
@@ -127,20 +144,28 @@ __device__ __forceinline__ int bag_insert_wave(const Bag &B, bool has, uint64_t 
                 }
                 if (last && probes >= nst) {
                     if (lane_id() == 0) atomicOr(&B.ctl->overflow, 1u);
-                    spill = false;
-                    placed = k;  // give up: the host sees the overflow flag
-                    inserted = 0;
+                    lost = true;  // give up: the host sees the overflow flag
                     break;
                 }
             }
         }
-        if (pending && my < placed) pending = false;
-        if (!spill) {
-            pending = false;
+#pragma unroll
+        for (int j = 0; j < A; j++) {
+            if (!pending[j]) continue;
+            if (lost && my[j] >= placed) inserted--;
+            if (my[j] < placed || !spill) pending[j] = false;
         }
-        mask = ballot(pending);
+        if (!spill) break;
     }
     return inserted;
+}
+
+// One element per lane.
+__device__ __forceinline__ int bag_insert_wave(const Bag &B, bool has, uint64_t e, uint32_t wave_gid,
+                                               uint32_t &wseq) {
+    const bool h[1] = {has};
+    const uint64_t x[1] = {e};
+    return bag_insert_wave_n<1>(B, h, x, wave_gid, wseq);
 }
 
 }  // namespace hipscc

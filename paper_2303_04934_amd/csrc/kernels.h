@@ -24,6 +24,14 @@ struct RoundCtl {
     uint32_t pad;
     unsigned long long fdeg;    // summed degree of the frontier ExtractAll produced
     unsigned long long claims;  // pairs (or vertices) claimed by this lane's search
+    uint32_t lsdepth;           // deepest local search (steps) of the last expand round
+    uint32_t tau_cur;           // VGC budget of the next round when a policy sets it
+    uint32_t mode_pref;         // policy's preferred mode for the next round (0 sparse, 1 dense)
+    uint32_t policy_calls;
+    uint32_t policy_fallbacks;
+    uint32_t snap_rounds, snap_depth;  // trace snapshot of the round's inputs
+    unsigned long long snap_nf, snap_fdeg, snap_claims;
+    uint32_t pad2;
 };
 
 // Call-level values shared by all lanes.
@@ -47,7 +55,7 @@ constexpr uint32_t kErrTable = 1u;      // reach table probe limit exceeded
 constexpr uint32_t kErrCapacity = 2u;   // frontier / heavy list capacity exceeded
 constexpr uint32_t kErrUnfinished = 4u; // a vertex had no SCC key at the end
 
-constexpr int kQcap = 512;  // local queue entries per wave (LDS)
+constexpr int kQcap = 256;  // local queue entries per wave (LDS)
 constexpr int kQmask = kQcap - 1;
 constexpr int kStepArcs = 256;  // arcs a wave commits to per local-search step
 constexpr int kHeavyChunk = 4096;  // arcs per edge-parallel work item
@@ -80,6 +88,7 @@ struct Search {
     int32_t seeds;          // 0: automatic
     int32_t heavy_deg;
     uint32_t vgc_cut;       // rounds whose frontier has at least this many entries skip local search
+    uint32_t tau_from_rc;   // 1: the budget of each round is rc->tau_cur (set by the policy)
 };
 
 // ------------------------------------------------------------- utilities ----
@@ -284,6 +293,24 @@ __global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, uint64_t 
 }
 
 // ---------------------------------------------------------------- expand ----
+// Reach-table claim that starts from an already loaded first probe: slot h
+// held `cur`.  1: new pair claimed; 0: already present; -1: probe limit hit.
+__device__ __forceinline__ int claim_pair_at(uint64_t *T, uint64_t mask, uint32_t limit, uint64_t key, uint64_t h,
+                                             uint64_t cur) {
+    for (uint32_t p = 0; p <= limit; p++) {
+        if (p > 0) cur = ld_relaxed64(T + h);
+        if (cur == key) return 0;
+        if (cur == kEmpty64) {
+            const unsigned long long old = atomicCAS((unsigned long long *)(T + h), (unsigned long long)kEmpty64,
+                                                     (unsigned long long)key);
+            if (old == kEmpty64) return 1;
+            if (old == key) return 0;
+        }
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
 // One frontier round with vertical granularity control (Section 3.1-3.2).
 //
 // Each wavefront takes a group of frontier entries and runs one bounded local
@@ -294,18 +321,27 @@ __global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, uint64_t 
 // Section 3.2 (successful or not).  Newly claimed entries go to the local
 // queue while it has room, otherwise straight to the hash bag.  When the
 // budget is spent or the queue is empty, what is left in the queue is
-// inserted into the bag, i.e. the next frontier (Section 3.2).  With tau <= 1
-// nothing is searched locally and this is one plain BFS round (Algorithm 2/3).
-// Entries with more than heavy_deg arcs are deferred to k_expand_heavy, which
-// spreads one adjacency list over the whole grid (Section 3.2: vertices with
-// more than tau neighbours are processed edge-parallel).
+// inserted into the bag, i.e. the next frontier (Section 3.2).  With tau <= 1,
+// or when the frontier alone fills every wavefront, nothing is searched
+// locally and this is one plain round (Algorithm 2/3).  Entries with more than
+// heavy_deg arcs are deferred to k_expand_heavy, which spreads one adjacency
+// list over the whole grid (Section 3.2: vertices with more than tau
+// neighbours are processed edge-parallel).
+//
+// A local search is a chain of dependent memory accesses, one level per step,
+// so its latency is the critical path of a round.  Queue entries therefore
+// carry their adjacency range, fetched when the entry is claimed in parallel
+// with the claim itself, and a claim issues the target's label, its first
+// reach-table probe and its offsets together.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
-    __shared__ uint64_t Qs[kWavesPerBlock][kQcap];
+    __shared__ uint64_t Qk[kWavesPerBlock][kQcap];   // (vertex, source) keys
+    __shared__ int2 Qr[kWavesPerBlock][kQcap];       // (first arc, degree)
     __shared__ int32_t Sx[kWavesPerBlock][4][kWave];
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
-    uint64_t *Q = Qs[wv];
+    uint64_t *Q = Qk[wv];
+    int2 *R = Qr[wv];
     int32_t *sexcl = Sx[wv][0];
     int32_t *sbeg = Sx[wv][1];
     int32_t *ssrc = Sx[wv][2];
@@ -314,15 +350,19 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
     uint32_t nF = ld_relaxed(&rc->nF[S.par]);
     if (nF == 0) return;
     if (nF > S.fcap) nF = (uint32_t)S.fcap;  // overflow was flagged by ExtractAll
+    const int32_t tau = S.tau_from_rc ? (int32_t)ld_relaxed(&rc->tau_cur) : S.tau;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rc->rounds += 1;
         rc->fdeg = 0;
+        rc->lsdepth = 0;
     }
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + wv;
+    // Seeds per wave: one group per wave when the frontier fits, so a round
+    // lasts one local search rather than several in sequence.
     uint32_t G = (uint32_t)S.seeds;
     if (G == 0) {
-        G = (nF + 2 * nwaves - 1) / (2 * nwaves);
+        G = (nF + nwaves - 1) / nwaves;
         if (G > 64) G = 64;
         if (G < 1) G = 1;
     }
@@ -330,7 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
     // Local search exists to give each task enough work when the frontier is
     // too small to keep the machine busy (Section 3.1); a frontier that
     // already fills every wavefront runs as a plain round.
-    const bool vgc = S.tau > 1 && nF < S.vgc_cut;
+    const bool vgc = tau > 1 && nF < S.vgc_cut;
+    uint32_t depth = 0;
     uint32_t wseq = 0;
     unsigned long long c_seeds = 0, c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
 
@@ -338,13 +379,21 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
     while (grp < ngroups) {
         const uint32_t start = grp * G;
         const int cnt = (int)((nF - start) < G ? (nF - start) : G);
-        if (lane < cnt) Q[lane] = S.F[start + lane];
+        if (lane < cnt) {
+            const uint64_t e = S.F[start + lane];
+            const int32_t u = key_vertex(e);
+            const int32_t b0 = S.off[u];
+            Q[lane] = e;
+            R[lane] = make_int2(b0, S.off[u + 1] - b0);
+        }
         c_seeds += (unsigned long long)cnt;
         int head = 0, tail = cnt;
         long long t = 0;
-        const long long budget = vgc ? (long long)S.tau * cnt : 0;
+        const long long budget = vgc ? (long long)tau * cnt : 0;
         wave_lds_sync();
+        uint32_t steps = 0;
         while (head < tail && (!vgc || t < budget)) {
+            steps++;
             const int avail = tail - head;
             const int k = avail < kWave ? avail : kWave;
             uint64_t e = 0;
@@ -352,10 +401,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
             uint32_t s = 0;
             if (lane < k) {
                 e = Q[(head + lane) & kQmask];
-                const int32_t u = key_vertex(e);
+                const int2 r2 = R[(head + lane) & kQmask];
+                beg = r2.x;
+                d = r2.y;
                 s = key_source(e);
-                beg = S.off[u];
-                d = S.off[u + 1] - beg;
                 if (MODE == kMulti) lab = S.srclab[s];
             }
             // candidate heavy entries (deferred to the edge-parallel kernel)
@@ -410,6 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
                 const int a = base + lane;
                 bool claimed = false;
                 uint64_t ne = 0;
+                int2 nr = make_int2(0, 0);
                 if (a < D) {
                     int lo = 0, hi = kk - 1;
                     while (lo < hi) {
@@ -418,19 +468,38 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
                     }
                     const int32_t w = S.adj[sbeg[lo] + (a - sexcl[lo])];
                     const uint32_t src = (uint32_t)ssrc[lo];
+                    ne = pair_key(w, src);
                     c_arcs++;
                     if (MODE == kSingle) {
                         c_att++;
-                        claimed = claim_bit(S.vis, w);
+                        const uint32_t bit = 1u << (w & 31);
+                        uint32_t *word = S.vis + (w >> 5);
+                        if (vgc) {
+                            // latency-bound regime: one atomic, offsets fetched alongside
+                            const int32_t o0 = S.off[w], o1 = S.off[w + 1];
+                            claimed = (atomicOr(word, bit) & bit) == 0;
+                            nr = make_int2(o0, o1 - o0);
+                        } else {
+                            // throughput regime: skip the atomic for visited targets
+                            claimed = !(ld_relaxed(word) & bit) && (atomicOr(word, bit) & bit) == 0;
+                        }
                     } else {
-                        if (S.label[w] == slab[lo]) {
+                        const uint64_t h = mix64(ne) & S.tmask;
+                        const int32_t lw = S.label[w];
+                        const uint64_t t0 = ld_relaxed64(S.table + h);
+                        int32_t o0 = 0, o1 = 0;
+                        if (vgc) {
+                            o0 = S.off[w];
+                            o1 = S.off[w + 1];
+                        }
+                        if (lw == slab[lo]) {
                             c_att++;
-                            const int c = claim_pair(S.table, S.tmask, S.probe_limit, pair_key(w, src));
+                            const int c = claim_pair_at(S.table, S.tmask, S.probe_limit, ne, h, t0);
                             if (c < 0) atomicOr(&rc->err, kErrTable);
                             claimed = c == 1;
                         }
+                        nr = make_int2(o0, o1 - o0);
                     }
-                    ne = pair_key(w, src);
                 }
                 const uint64_t cmask = ballot(claimed);
                 if (cmask == 0) continue;
@@ -438,12 +507,16 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
                 c_claims += claimed ? 1 : 0;
                 const int room = vgc ? kQcap - (tail - head) : 0;
                 const int r = rank_below(cmask);
-                if (claimed && r < room) Q[(tail + r) & kQmask] = ne;
+                if (claimed && r < room) {
+                    Q[(tail + r) & kQmask] = ne;
+                    R[(tail + r) & kQmask] = nr;
+                }
                 tail += nc < room ? nc : room;
                 c_ins += (unsigned long long)bag_insert_wave(S.bag, claimed && r >= room, ne, wave_gid, wseq);
             }
             wave_lds_sync();
         }
+        depth = steps > depth ? steps : depth;
         // flush the rest of the local queue into the next frontier
         for (int i = head; i < tail; i += kWave) {
             const bool h = i + lane < tail;
@@ -455,6 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
         if (lane == 0) nxt = atomicAdd(&rc->work[S.par], 1u) + nwaves;
         grp = wave_bcast_u(nxt, 0);
     }
+    if (lane == 0 && depth > 0) atomicMax(&rc->lsdepth, depth);
     unsigned long long c[kNumCtr] = {c_seeds, c_exp, c_arcs, c_att, c_claims, c_ins};
     const unsigned long long t = block_flush_ctr(S.cn->c[blockIdx.x % kCtrStripes][S.kind], c);
     if (threadIdx.x == kCtrClaims && t) atomicAdd(&rc->claims, t);
@@ -554,8 +628,21 @@ __global__ __launch_bounds__(kBlock) void k_pull(int32_t n, const int32_t *off, 
         }
     }
     block_add_u32(&rc->nF[par ^ 1], found_cnt);
-    unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, 0, 0, 0};
-    block_flush_ctr(cn->c[blockIdx.x % kCtrStripes][kKindPull], c);
+    // pull claims count as the lane's claims (visited fraction feature)
+    unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, 0, (unsigned long long)found_cnt, 0};
+    const unsigned long long t = block_flush_ctr(cn->c[blockIdx.x % kCtrStripes][kKindPull], c);
+    if (threadIdx.x == kCtrClaims && t) atomicAdd(&rc->claims, t);
+}
+
+// Trace mode: snapshot the inputs of the coming round (the policy features).
+__global__ void k_trace_snap(RoundCtl *rc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        rc->snap_nf = (unsigned long long)rc->nF[0] + rc->nF[1];
+        rc->snap_fdeg = rc->fdeg;
+        rc->snap_claims = rc->claims;
+        rc->snap_rounds = rc->rounds;
+        rc->snap_depth = rc->lsdepth;
+    }
 }
 
 __global__ void k_round_end(RoundCtl *rc, int par) {

@@ -16,8 +16,9 @@ constexpr int kPolicyHidden = 32;
 constexpr int kPolicyOut = 8;
 constexpr int kPolicyFloats = kPolicyHidden * kPolicyIn + kPolicyHidden + kPolicyHidden * kPolicyHidden +
                               kPolicyHidden + kPolicyOut * kPolicyHidden + kPolicyOut;
-// VGC budgets of the four classes; class c with mode m is output 2 c + m.
-constexpr int kPolicyTau[4] = {64, 256, 1024, 4096};
+// VGC budgets of the four classes (64, 256, 1024, 4096); class c with mode m
+// is output 2 c + m.
+__host__ __device__ __forceinline__ uint32_t policy_tau(int c) { return 64u << (2 * c); }
 
 struct Policy {
     float *w = nullptr;    // device weights
@@ -65,6 +66,74 @@ __global__ __launch_bounds__(64) void k_policy_rows(const float *W, const float 
     const int r = blockIdx.x;
     if (r >= rows) return;
     policy_forward_wave(W, feats + (int64_t)r * kPolicyIn, scores + (int64_t)r * kPolicyOut, h1, h2);
+}
+
+// Round features (all float32, computed on the device from the lane state):
+//   0 log2(1 + frontier size)
+//   1 log2(1 + summed degree of the frontier)
+//   2 visited fraction: entries claimed so far / subproblem size
+//   3 log2(1 + round index)
+//   4 log2(1 + steps of the deepest local search of the previous round)
+__device__ __forceinline__ void policy_features(float nf, float fdeg, float claims, float nsub, float round,
+                                                float depth, float *x) {
+    x[0] = log2f(1.f + nf);
+    x[1] = log2f(1.f + fdeg);
+    const float v = nsub > 0.f ? claims / nsub : 0.f;
+    x[2] = v < 0.f ? 0.f : (v > 1.f ? 1.f : v);
+    x[3] = log2f(1.f + round);
+    x[4] = log2f(1.f + depth);
+}
+
+// Host copy of the same formulas, for trace rows.
+inline void policy_features_host(float nf, float fdeg, float claims, float nsub, float round, float depth, float *x) {
+    x[0] = std::log2(1.f + nf);
+    x[1] = std::log2(1.f + fdeg);
+    const float v = nsub > 0.f ? claims / nsub : 0.f;
+    x[2] = v < 0.f ? 0.f : (v > 1.f ? 1.f : v);
+    x[3] = std::log2(1.f + round);
+    x[4] = std::log2(1.f + depth);
+}
+
+// Picks the next round's schedule for one search lane: the budget class and
+// frontier mode with the highest predicted rate among the allowed actions
+// (mode_mask bit m allows mode m).  Non-finite scores fall back to the fixed
+// schedule.  Writes the lane's tau_cur / mode_pref (fields given by pointer so
+// that this header does not depend on the round-control layout).
+__global__ __launch_bounds__(64) void k_policy_round(const float *W, const uint32_t *nF2, const unsigned long long *fdeg,
+                                                     const unsigned long long *claims, const uint32_t *rounds,
+                                                     const uint32_t *lsdepth, float nsub, uint32_t mode_mask,
+                                                     uint32_t fallback_tau, uint32_t *tau_cur, uint32_t *mode_pref,
+                                                     uint32_t *calls, uint32_t *fallbacks) {
+    __shared__ float x[kPolicyIn], h1[kPolicyHidden], h2[kPolicyHidden], y[kPolicyOut];
+    const uint32_t nf = nF2[0] + nF2[1];
+    if (nf == 0) return;
+    if (threadIdx.x == 0)
+        policy_features((float)nf, (float)*fdeg, (float)*claims, nsub, (float)*rounds, (float)*lsdepth, x);
+    __syncthreads();
+    policy_forward_wave(W, x, y, h1, h2);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int best = -1;
+        float bv = 0.f;
+        bool ok = true;
+        for (int a = 0; a < kPolicyOut; a++) {
+            if (!isfinite(y[a])) ok = false;
+            if (!((mode_mask >> (a & 1)) & 1u)) continue;
+            if (best < 0 || y[a] > bv) {
+                best = a;
+                bv = y[a];
+            }
+        }
+        *calls += 1;
+        if (!ok || best < 0) {
+            *tau_cur = fallback_tau;
+            *mode_pref = 0;
+            *fallbacks += 1;
+        } else {
+            *tau_cur = policy_tau(best >> 1);
+            *mode_pref = (uint32_t)(best & 1);
+        }
+    }
 }
 
 inline void policy_release(Policy &p) {

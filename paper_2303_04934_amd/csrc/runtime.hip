@@ -83,6 +83,12 @@ struct scc_ctx {
     double tm_ms[3] = {0, 0, 0};
     int64_t tm_launches[3] = {0, 0, 0};
     int64_t dense_rounds = 0;
+    // options.trace rows and the round events that time them
+    bool tracing = false;
+    std::vector<float> trace;
+    hipEvent_t rev[2][2] = {};
+    int32_t epoch = 0;
+    uint64_t explore_state = 0;
     // phase events (statistics)
     std::vector<hipEvent_t> pev;
     size_t pev_used = 0;
@@ -249,7 +255,7 @@ void check_opts(scc_ctx *c, const scc_options_t &o) {
         set_err(c, "table_init must be 0 or a power of two");
         throw Fail{SCC_EINVAL};
     }
-    if (o.policy != 0 && o.policy != 1) { set_err(c, "policy must be 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (o.policy < 0 || o.policy > 2) { set_err(c, "policy must be 0, 1 or 2"); throw Fail{SCC_EINVAL}; }
     if (o.dense < -1 || o.dense > 1) { set_err(c, "dense must be -1, 0 or 1"); throw Fail{SCC_EINVAL}; }
 }
 
@@ -315,6 +321,11 @@ struct Lane {
     uint64_t nf = 0;
     double growth = 1.0;     // frontier growth per round (host estimate)
     int64_t rounds = 0;
+    // state before the round, for trace rows
+    uint64_t fdeg = 0, claims = 0;
+    uint32_t depth = 0;
+    uint32_t tau_used = 0;
+    int64_t nsub = 1;
     // single source
     bool dense = false, have_list = true;
     const int32_t *roff = nullptr, *radj = nullptr;
@@ -336,6 +347,25 @@ struct DriveParams {
 // ExtractAll grid: each block walks 256 stripes (16K slots) per step, and the
 // last-block ticket costs one atomic per block, so a modest grid suffices.
 unsigned extract_blocks(scc_ctx *c) { return (unsigned)std::max(c->num_cu / 2, 1); }
+
+// Before a round: the learned policy picks the round's budget (and preferred
+// mode) on the device; exploration draws a random budget class.
+void launch_policy(scc_ctx *c, Lane &L, const scc_options_t &o, int dense_opt) {
+    Search &S = L.S;
+    if (o.policy == 1 && c->policy.loaded) {
+        RoundCtl *rc = S.rc;
+        const uint32_t mask = L.mode == kMulti ? 1u : (dense_opt == -1 ? 3u : (dense_opt == 1 ? 2u : 1u));
+        hipLaunchKernelGGL(k_policy_round, dim3(1), dim3(64), 0, c->stream, c->policy.w, rc->nF, &rc->fdeg, &rc->claims,
+                           &rc->rounds, &rc->lsdepth, (float)L.nsub, mask, (uint32_t)std::max(o.tau, 0), &rc->tau_cur,
+                           &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks);
+        LAUNCHCHK("k_policy_round");
+        S.tau_from_rc = 1;
+    } else if (o.policy == 2) {
+        c->explore_state = mix64(c->explore_state + 0x9E3779B97F4A7C15ull);
+        S.tau = (int32_t)policy_tau((int)(c->explore_state >> 62));
+        S.tau_from_rc = 0;
+    }
+}
 
 void launch_sparse(scc_ctx *c, Lane &L, int slot, bool fdeg) {
     Search &S = L.S;
@@ -418,14 +448,22 @@ void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
 // expands entries claimed in the previous round, so a search has at most
 // (claimable entries + 1) rounds; the launch count guards the loop.
 void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
-    const int dense_opt = P.o->dense;
+    const scc_options_t &o = *P.o;
+    const int dense_opt = o.dense;
+    const bool use_policy = o.policy == 1 && c->policy.loaded;
+    const bool fdeg_always = use_policy || c->tracing;
     for (int i = 0; i < nl; i++) {
-        lanes[i].live = true;
-        lanes[i].par = 0;
-        lanes[i].nf = 1;
-        lanes[i].growth = 64.0;
-        lanes[i].dense = dense_opt == 1 && lanes[i].mode == kSingle;
-        lanes[i].have_list = true;
+        Lane &L = lanes[i];
+        L.live = true;
+        L.par = 0;
+        L.nf = 1;
+        L.growth = 64.0;
+        L.dense = dense_opt == 1 && L.mode == kSingle;
+        L.have_list = true;
+        L.fdeg = L.claims = 0;
+        L.depth = 0;
+        L.rounds = 0;
+        L.nsub = std::max<int64_t>(P.nsub, 1);
     }
     const uint64_t arcs_on = (uint64_t)std::max<int64_t>(P.m / 14, 1);
     const int64_t back_off = std::max<int64_t>(P.nsub / 24, 1);
@@ -434,6 +472,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
     uint64_t limit = (uint64_t)P.n + 64;
     for (int i = 0; i < nl; i++)
         if (lanes[i].mode == kMulti) limit = std::max<uint64_t>(limit, 2 * *lanes[i].tslots + 64);
+    bool was_dense[2] = {false, false};
     for (;;) {
         bool any = false, watch = false;
         for (int i = 0; i < nl; i++) {
@@ -447,17 +486,25 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 watch = true;
         }
         if (!any) break;
-        const int k = watch ? 1 : K;
+        const int k = (watch || c->tracing) ? 1 : K;
         for (int r = 0; r < k; r++)
             for (int i = 0; i < nl; i++) {
                 Lane &L = lanes[i];
                 if (!L.live) continue;
+                if (c->tracing) {
+                    hipLaunchKernelGGL(k_trace_snap, dim3(1), dim3(64), 0, c->stream, L.S.rc);
+                    LAUNCHCHK("k_trace_snap");
+                }
+                launch_policy(c, L, o, dense_opt);
+                if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][0], c->stream));
+                was_dense[L.id] = L.dense;
                 if (L.dense) {
                     launch_dense(c, L);
                     c->dense_rounds++;
                 } else {
-                    launch_sparse(c, L, r, watch && L.mode == kSingle && dense_opt != 0);
+                    launch_sparse(c, L, r, fdeg_always || (watch && L.mode == kSingle && dense_opt != 0));
                 }
+                if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][1], c->stream));
             }
         launched += (uint64_t)k;
         sync_ctl(c);
@@ -476,15 +523,34 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 }
                 c->tm_launches[kind] += nslots;
             }
-            if (L.mode == kMulti && (rc.err & kErrTable)) {
-                restart_multi(c, L, P);
-                continue;
-            }
             if ((rc.err & kErrCapacity) || c->hctl->bag[L.id].overflow) {
                 set_err(c, "frontier capacity exceeded (err=%u, bag overflow=%u)", rc.err, c->hctl->bag[L.id].overflow);
                 throw Fail{SCC_EINTERNAL};
             }
             const uint64_t nf_new = (uint64_t)rc.nF[0] + rc.nF[1];
+            if (c->tracing && rc.rounds > L.rounds) {
+                float x[kPolicyIn];
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, c->rev[L.id][0], c->rev[L.id][1]));
+                hipscc::policy_features_host((float)rc.snap_nf, (float)rc.snap_fdeg, (float)rc.snap_claims,
+                                             (float)L.nsub, (float)rc.snap_rounds, (float)rc.snap_depth, x);
+                const float tau = (float)(use_policy ? rc.tau_cur : (uint32_t)std::max(L.S.tau, 0));
+                const float row[SCC_TRACE_FIELDS] = {
+                    (float)(L.mode == kMulti ? 2 : (was_dense[L.id] ? 1 : 0)), x[0], x[1], x[2], x[3], x[4], tau, ms,
+                    (float)(rc.claims - rc.snap_claims), (float)nf_new, (float)c->epoch, (float)P.n};
+                c->trace.insert(c->trace.end(), row, row + SCC_TRACE_FIELDS);
+            }
+            if (L.mode == kMulti && (rc.err & kErrTable)) {
+                if (P.st) P.st->rounds_multi += rc.rounds;  // rounds of the abandoned attempt
+                restart_multi(c, L, P);
+                L.fdeg = L.claims = 0;
+                L.depth = 0;
+                L.rounds = 0;
+                continue;
+            }
+            L.fdeg = rc.fdeg;
+            L.claims = rc.claims;
+            L.depth = rc.lsdepth;
             if (L.nf > 0 && nf_new > 0) L.growth = std::pow((double)nf_new / (double)L.nf, 1.0 / (double)(L.dense ? 1 : k));
             L.nf = nf_new;
             L.rounds = rc.rounds;
@@ -494,11 +560,20 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
             }
             L.par = rc.nF[0] ? 0 : 1;
             if (L.mode != kSingle || dense_opt == 0) continue;
-            if (!L.dense && (dense_opt == 1 || (watch && rc.fdeg > arcs_on))) {
+            bool to_dense, to_sparse;
+            if (use_policy && dense_opt == -1) {
+                // the policy's preferred mode for the next round
+                to_dense = !L.dense && rc.mode_pref == 1;
+                to_sparse = L.dense && rc.mode_pref == 0;
+            } else {
+                to_dense = !L.dense && (dense_opt == 1 || (watch && rc.fdeg > arcs_on));
+                to_sparse = L.dense && dense_opt == -1 && (int64_t)L.nf < back_off;
+            }
+            if (to_dense) {
                 L.dense = true;
                 L.have_list = true;
                 switched = true;
-            } else if (L.dense && dense_opt == -1 && (int64_t)L.nf < back_off) {
+            } else if (to_sparse) {
                 // back to sparse: the bitmap frontier becomes the list F
                 fill_u32(c, &L.S.rc->listpos, 1, 0u);
                 hipLaunchKernelGGL(k_bitmap_to_list, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, L.n,
@@ -514,6 +589,13 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
             throw Fail{SCC_EINTERNAL};
         }
         K = switched || watch ? 1 : std::min(K * 2, kMaxSlots);
+    }
+    if (P.st) {
+        for (int i = 0; i < nl; i++) {
+            P.st->policy_calls += c->hctl->lane[lanes[i].id].policy_calls;
+            P.st->policy_fallbacks += c->hctl->lane[lanes[i].id].policy_fallbacks;
+        }
+        if (o.policy == 1 && !c->policy.loaded) P.st->policy_fallbacks += (int64_t)launched;
     }
 }
 
@@ -593,6 +675,13 @@ void init_call(scc_ctx *c, scc_stats_t *st, int64_t n, int64_t m, const scc_opti
         c->tm_launches[i] = 0;
     }
     c->dense_rounds = 0;
+    c->tracing = o && o->trace;
+    c->trace.clear();
+    c->epoch = 0;
+    c->explore_state = o ? o->seed * 0x2545F4914F6CDD1Dull + 7 : 7;
+    if (c->tracing && !c->rev[0][0])
+        for (auto &a : c->rev)
+            for (auto &e : a) HIPCHK(hipEventCreate(&e));
     c->plog.clear();
     c->pev_used = 0;
     if (st) {
@@ -820,6 +909,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             LAUNCHCHK("k_seed_multi");
         }
         DP.nsub = active;
+        c->epoch = epoch;
         drive(c, L, 2, DP);
         phase_end(c, ph);
         const uint32_t k = c->hctl->sh.k;
@@ -1064,6 +1154,9 @@ void scc_destroy(scc_ctx_t *c) {
             for (auto &e : b)
                 if (e) (void)hipEventDestroy(e);
     for (auto e : c->pev) (void)hipEventDestroy(e);
+    for (auto &a : c->rev)
+        for (auto &e : a)
+            if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1305,6 +1398,16 @@ scc_status scc_policy_eval(scc_ctx_t *c, const float *feats, int32_t rows, float
         if (rows == 0) return;
         int rc = policy_eval_host(c->policy, feats, rows, scores, c->stream);
         if (rc != 0) { set_err(c, "policy evaluation failed (%d)", rc); throw Fail{SCC_EHIP}; }
+    });
+}
+
+scc_status scc_trace_read(scc_ctx_t *c, float *out, int64_t cap, int64_t *n_rows) {
+    return guard(c, [&] {
+        if (!n_rows || cap < 0 || (cap > 0 && !out)) { set_err(c, "bad arguments"); throw Fail{SCC_EINVAL}; }
+        const int64_t rows = (int64_t)(c->trace.size() / SCC_TRACE_FIELDS);
+        *n_rows = rows;
+        const int64_t k = std::min(rows, cap);
+        if (k > 0) memcpy(out, c->trace.data(), sizeof(float) * (size_t)k * SCC_TRACE_FIELDS);
     });
 }
 

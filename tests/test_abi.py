@@ -40,7 +40,7 @@ def test_struct_layouts_match_header():
     # the Python mirrors must have the sizes the C compiler gives the structs
     from paper_2303_04934_amd import _native
     assert ctypes.sizeof(_native.Graph) == 8 + 4 * 8
-    assert ctypes.sizeof(_native.Options) == 4 * 6 + 8 + 4 * 4 + 8 + 4 + 4 + 4 * 6
+    assert ctypes.sizeof(_native.Options) == 4 * 6 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4 * 5
     assert ctypes.sizeof(_native.Stats) == 6 * 8 + 18 * 8 + 3 * 8 * 3 + 3 * 8
 
 

@@ -229,3 +229,17 @@ def test_dense_reach_matches_oracle(gpu):
             off, adj = (g.out_off, g.out_adj) if d == 0 else (g.in_off, g.in_adj)
             want = oracle.reach_pairs(g.n, off, adj, lab, [int(np.argmax(np.diff(g.out_off)))])
             assert np.array_equal(sorted_pairs(got), want)
+
+
+def test_policy_and_exploration_do_not_change_labels(gpu):
+    rng = np.random.default_rng(9)
+    g = graphgen.knn(50000, 5, 5, 0.01, seed=21)
+    w = (rng.standard_normal(gpu.POLICY_FLOATS) * 0.5).astype(np.float32)
+    gpu.policy_load(w)
+    st = check_labels(gpu, g, gpu.default_options(policy=1), name="knn50k learned(random weights)")
+    assert st["policy_calls"] > 0
+    st = check_labels(gpu, g, gpu.default_options(policy=2, trace=1), name="knn50k explore+trace")
+    rows = gpu.trace_read()
+    assert rows.shape[1] == gpu.TRACE_FIELDS and len(rows) == st["rounds_first"] + st["rounds_multi"]
+    assert set(np.unique(rows[:, 6])) <= {64.0, 256.0, 1024.0, 4096.0}
+    check_labels(gpu, graphgen.rmat(13, 16, seed=22), gpu.default_options(policy=1, dense=-1), name="rmat13 learned")
