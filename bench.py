@@ -33,6 +33,7 @@ WORKLOADS = {
 }
 KERNEL_NAMES = ["hipscc::k_expand<0>", "hipscc::k_expand<1>", "hipscc::k_pull"]
 KERNEL_SHORT = ["k_expand0", "k_expand1", "k_pull"]
+NK = len(KERNEL_NAMES)
 
 
 def source_hash():
@@ -81,7 +82,19 @@ def main():
     ap.add_argument("--tau", type=int, default=512)
     ap.add_argument("--cpu-runs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--policy", type=int, default=0, help="0 fixed budget, 1 learned per-round policy")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "copies": 5}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
@@ -100,15 +113,18 @@ def main():
           file=sys.stderr, flush=True)
     dg = scc.to_device(g, "cuda:0")
     out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
-    opts = scc.default_options(tau=args.tau, timing=1, validate=0)
+    opts = scc.default_options(tau=args.tau, timing=1, validate=0, policy=args.policy)
+    if args.policy == 1:
+        import numpy as np
+        scc.policy_load(np.load(os.path.join(ROOT, "paper_2303_04934_amd", "policy_weights.npy")))
     for _ in range(args.warmup):
         scc.scc_labels(dg, opts, out=out)
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    ms_exp = [0.0, 0.0, 0.0]
-    launches = [0, 0, 0]
-    bexp = [0, 0, 0]
+    ms_exp = [0.0] * NK
+    launches = [0] * NK
+    bexp = [0] * NK
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -118,7 +134,7 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     for st in stats:
-        for m in (0, 1, 2):
+        for m in range(NK):
             ms_exp[m] += st["ms_kernel"][m]
             launches[m] += st["launches_kernel"][m]
             bexp[m] += st["bytes_kernel"][m]
@@ -130,9 +146,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": g.n, "m": g.m, "seed": 1000 + cfg,
-                   "tau": args.tau, "shrink": args.shrink},
+                   "tau": args.tau, "policy": "learned" if args.policy == 1 else "fixed",
+                   "shrink": args.shrink},
     }
-    dom = max(range(3), key=lambda i: ms_exp[i])
+    dom = max(range(NK), key=lambda i: ms_exp[i])
     if launches[dom] > 0 and ms_exp[dom] > 0:
         per_launch_ms = ms_exp[dom] / launches[dom]
         per_launch_bytes = bexp[dom] / launches[dom]
@@ -149,7 +166,7 @@ def main():
                                          "arcs_scanned",
                                          "claims", "bag_inserts", "table_restarts", "bytes_alg")}
     line["stats"]["alg_GBps_whole_step"] = last["bytes_alg"] / dt / 1e9
-    line["stats"]["kernel_ms_per_step"] = {KERNEL_SHORT[i]: ms_exp[i] / args.steps for i in range(3)}
+    line["stats"]["kernel_ms_per_step"] = {KERNEL_SHORT[i]: ms_exp[i] / args.steps for i in range(NK)}
     if not args.no_cpu_baseline:
         want, cb = cpu_baseline(g, args.cpu_runs)
         line["cpu_baseline"] = cb

@@ -107,6 +107,12 @@ typedef struct {
     int32_t reserved[5];
 } scc_options_t;
 
+/* Frontier kernels timed with options.timing. */
+#define SCC_KERNEL_EXPAND_SINGLE 0  /* sparse single-source expand round */
+#define SCC_KERNEL_EXPAND_MULTI 1   /* multi-source expand round */
+#define SCC_KERNEL_PULL 2           /* dense pull round */
+#define SCC_KERNELS 3
+
 /* Per-call statistics (host struct, written when non-NULL).  Times are
  * milliseconds measured with HIP events on the context's stream.  The five
  * phases follow the paper's breakdown (Section 4 / Figure 8): trimming,
@@ -131,16 +137,16 @@ typedef struct {
     int64_t policy_calls;     /* rounds decided by the learned policy */
     int64_t policy_fallbacks; /* rounds where the policy output was unusable */
     int64_t bytes_alg;        /* algorithmic HBM bytes of the whole call */
-    /* with options.timing: for the frontier kernels [0] sparse single-source
-     * expand, [1] multi-source expand, [2] dense pull, the summed event time
-     * of their launches, the number of launches and their algorithmic bytes.
-     * Expand: frontier entry 8, offsets 8 per expanded entry, 4 per scanned
-     * arc, 4 per claim attempt, 8 (multi) or 4 (single) per claim, 8 per bag
-     * insert.  Pull: visited and next words (n/4), offsets 8 per unvisited
-     * vertex, 8 per scanned arc (target id + frontier word). */
-    double ms_kernel[3];
-    int64_t launches_kernel[3];
-    int64_t bytes_kernel[3];
+    /* with options.timing: for the frontier kernels (SCC_KERNEL_*) the summed
+     * event time of their launches, the number of launches and their
+     * algorithmic bytes.  Expand: frontier entry 8, offsets 8 per expanded
+     * entry, 4 per scanned arc, 4 per claim attempt, 8 (multi) or 4 (single)
+     * per claim, 8 per bag insert.  Pull: visited and
+     * next words (n/4), offsets 8 per unvisited vertex, 8 per scanned arc
+     * (target id + frontier word). */
+    double ms_kernel[SCC_KERNELS];
+    int64_t launches_kernel[SCC_KERNELS];
+    int64_t bytes_kernel[SCC_KERNELS];
     int64_t reserved[3];
 } scc_stats_t;
 

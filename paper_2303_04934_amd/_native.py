@@ -20,6 +20,11 @@ class Graph(ctypes.Structure):
                 ("in_off", ctypes.c_void_p), ("in_adj", ctypes.c_void_p)]
 
 
+# frontier kernels timed with options.timing (SCC_KERNEL_* in hipscc.h)
+KERNEL_NAMES = ["k_expand<0>", "k_expand<1>", "k_pull"]
+KERNELS = len(KERNEL_NAMES)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_int32), ("beta", ctypes.c_float), ("lambda_log2", ctypes.c_int32),
                 ("sigma", ctypes.c_int32), ("kappa", ctypes.c_int32), ("alpha", ctypes.c_float),
@@ -36,8 +41,8 @@ class Stats(ctypes.Structure):
                                                "entries_expanded", "arcs_scanned", "claim_attempts", "claims",
                                                "bag_inserts", "bag_chunk_advances", "table_restarts", "trimmed",
                                                "n_scc", "policy_calls", "policy_fallbacks", "bytes_alg")] + \
-               [("ms_kernel", ctypes.c_double * 3), ("launches_kernel", ctypes.c_int64 * 3),
-                ("bytes_kernel", ctypes.c_int64 * 3), ("reserved", ctypes.c_int64 * 3)]
+               [("ms_kernel", ctypes.c_double * KERNELS), ("launches_kernel", ctypes.c_int64 * KERNELS),
+                ("bytes_kernel", ctypes.c_int64 * KERNELS), ("reserved", ctypes.c_int64 * 3)]
 
     def as_dict(self):
         d = {}

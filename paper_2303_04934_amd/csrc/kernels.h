@@ -9,6 +9,7 @@ namespace hipscc {
 enum { kCtrSeeds = 0, kCtrExpanded, kCtrArcs, kCtrAttempts, kCtrClaims, kCtrInserts, kNumCtr };
 constexpr int kCtrStripes = 32;
 // counter kinds: expand single-source, expand multi-source, pull, edge-parallel
+// Counter kinds: the work of each frontier kernel.
 enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavy = 3, kNumKinds = 4 };
 
 // Round control of one search lane (one direction of a search), in device
@@ -16,15 +17,14 @@ enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavy = 
 // counters can be reset while the next round's are in use.
 struct RoundCtl {
     uint32_t nF[2];        // frontier sizes
-    uint32_t work[2];      // dynamic work counters of the expand kernel
     uint32_t heavy_n[2];   // items deferred to the edge-parallel kernel
     uint32_t err;          // kErr* bits
     uint32_t rounds;       // rounds with a non-empty frontier
     uint32_t listpos;      // bitmap -> list conversion cursor
     uint32_t pad;
     unsigned long long fdeg;    // summed degree of the frontier ExtractAll produced
-    unsigned long long claims;  // pairs (or vertices) claimed by this lane's search
-    uint32_t lsdepth;           // deepest local search (steps) of the last expand round
+    unsigned long long claims;  // pairs (or vertices) claimed by this lane's search (folded at round end)
+    uint32_t lsdepth[2];        // deepest local search (steps) of the round of each parity (folded)
     uint32_t tau_cur;           // VGC budget of the next round when a policy sets it
     uint32_t mode_pref;         // policy's preferred mode for the next round (0 sparse, 1 dense)
     uint32_t policy_calls;
@@ -34,16 +34,64 @@ struct RoundCtl {
     uint32_t pad2;
 };
 
+// Striped round counters of one lane.  Atomics on one address from many
+// blocks serialise in the L2, so blocks spread them over kStripes cache
+// lines (block b uses line b % kStripes); one thread folds the lines into
+// RoundCtl when the round ends.
+constexpr int kStripes = 16;
+struct alignas(128) StripeLine {
+    unsigned long long claims;  // cumulative over the search
+    uint32_t depth;             // this round's deepest local search
+    uint32_t nf;                // this round's next-frontier size (dense rounds)
+    uint32_t work[2];           // dynamic group counters of the expand kernel, per parity
+    uint32_t pad[26];
+};
+static_assert(sizeof(StripeLine) == 128, "one cache line per stripe");
+struct LaneStripes {
+    StripeLine s[kStripes];
+};
+
+// Zeroes every stripe (all threads of one block take part).
+__device__ __forceinline__ void stripes_clear(LaneStripes *ls) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(ls);
+    for (uint32_t i = threadIdx.x; i < sizeof(LaneStripes) / 4; i += blockDim.x) w[i] = 0u;
+}
+
+// Round-end fold (one thread): claims and the round's local-search depth
+// into RoundCtl; this parity's work counters and the depth lines restart.
+__device__ __forceinline__ void stripes_fold(RoundCtl *rc, LaneStripes *ls, int par) {
+    unsigned long long c = 0;
+    uint32_t d = 0;
+    for (int i = 0; i < kStripes; i++) {
+        StripeLine &L = ls->s[i];
+        c += L.claims;
+        d = L.depth > d ? L.depth : d;
+        L.depth = 0;
+        L.work[par] = 0;
+    }
+    rc->claims = c;
+    rc->lsdepth[par] = d;
+}
+
 // Call-level values shared by all lanes.
 struct Shared {
     uint32_t k;            // sources selected for the batch
-    uint32_t fin;          // vertices finished so far (all batches)
     uint32_t first;        // first active permutation position (batch 1)
     uint32_t emit;         // pairs emitted by scc_reach
-    uint32_t nscc;         // canonical representatives
-    uint32_t trimmed;
     uint32_t bad;          // validation flags
-    uint32_t pad;
+};
+
+// Call-level counts that whole grids add to, striped like LaneStripes (block
+// b adds to line b % kStripes); the host sums the lines.
+struct alignas(128) CountLine {
+    uint32_t fin;          // vertices finished so far (all batches)
+    uint32_t trimmed;      // vertices finished by trimming
+    uint32_t nscc;         // canonical representatives
+    uint32_t pad[29];
+};
+static_assert(sizeof(CountLine) == 128, "one cache line per stripe");
+struct CountStripes {
+    CountLine s[kStripes];
 };
 
 // Work counters, striped over kCtrStripes slots to spread the atomics.
@@ -80,6 +128,7 @@ struct Search {
     uint64_t hcap;          // capacity of heavy (items)
     Bag bag;
     RoundCtl *rc;
+    LaneStripes *ls;
     Counters *cn;
     int32_t kind;           // counter kind of the expand kernel
     int32_t par;
@@ -116,6 +165,27 @@ __device__ __forceinline__ void block_add_u32(uint32_t *ctr, uint32_t x) {
     }
 }
 
+// Block-wide reservation: wave w of the block asks for cnt slots (the value
+// of lane 0 counts) and gets the first of its own range; one atomic per
+// block.  Every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_reserve(uint32_t *ctr, uint32_t cnt) {
+    __shared__ uint32_t want[kWavesPerBlock];
+    __shared__ uint32_t base_s;
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == 0) want[wv] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWavesPerBlock; w++) t += want[w];
+        base_s = t ? atomicAdd(ctr, t) : 0u;
+    }
+    __syncthreads();
+    uint32_t b = base_s;
+    for (int w = 0; w < wv; w++) b += want[w];
+    __syncthreads();  // want/base_s are rewritten by the next call
+    return b;
+}
+
 // Block-wide flush of the kNumCtr work counters into one stripe.  Returns, on
 // thread i < kNumCtr, the block's total of counter i.
 __device__ __forceinline__ unsigned long long block_flush_ctr(unsigned long long *dst, unsigned long long (&c)[kNumCtr]) {
@@ -137,14 +207,14 @@ __device__ __forceinline__ unsigned long long block_flush_ctr(unsigned long long
 // Section 4.1: a vertex with zero in- or out-degree is a singleton SCC.
 // Finished vertices store ~key (negative); key = v here.
 __global__ void k_trim(int32_t n, const int32_t *out_off, const int32_t *in_off, int32_t *label, int32_t do_trim,
-                       Shared *sh) {
+                       CountStripes *cs) {
     uint32_t cnt = 0;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const bool t = do_trim && (out_off[v + 1] == out_off[v] || in_off[v + 1] == in_off[v]);
         label[v] = t ? ~(int32_t)v : 0;
         cnt += t;
     }
-    block_add_u32(&sh->trimmed, cnt);
+    block_add_u32(&cs->s[blockIdx.x % kStripes].trimmed, cnt);
 }
 
 // ----------------------------------------------------- source selection ----
@@ -189,9 +259,7 @@ __global__ void k_select_sources(Perm P, uint32_t p0, uint32_t p1, const int32_t
         }
         bool act = l >= 0;
         uint64_t m = ballot(act);
-        uint32_t base = 0;
-        if (m && lane_id() == 0) base = atomicAdd(&sh->k, (uint32_t)popc64(m));
-        base = wave_bcast_u(base, 0);
+        const uint32_t base = block_reserve(&sh->k, (uint32_t)popc64(m));
         if (act) {
             uint32_t idx = base + rank_below(m);
             srcvert[idx] = v;
@@ -261,14 +329,16 @@ __global__ void k_premark(int32_t n, const int32_t *label, int32_t L, int32_t s_
     }
 }
 
-__global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_t *F, RoundCtl *rc) {
+__global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_t *F, RoundCtl *rc,
+                              LaneStripes *ls) {
+    if (blockIdx.x == 0) stripes_clear(ls);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const int32_t s = single_source(s_fixed, sh, P);
         if (s >= 0) F[0] = pair_key(s, 0);
         rc->nF[0] = s >= 0 ? 1u : 0u;
         rc->nF[1] = 0;
-        rc->work[0] = rc->work[1] = 0;
         rc->heavy_n[0] = rc->heavy_n[1] = 0;
+        rc->claims = 0;
         rc->rounds = 0;
         rc->err = 0;
     }
@@ -276,7 +346,8 @@ __global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_
 
 // Multi-source seed: claim (s_j, j) and put it in the frontier.
 __global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, uint64_t *T, uint64_t mask, uint32_t limit,
-                             uint64_t *F, RoundCtl *rc) {
+                             uint64_t *F, RoundCtl *rc, LaneStripes *ls) {
+    if (blockIdx.x == 0) stripes_clear(ls);
     const uint32_t k = sh->k;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
         uint64_t key = pair_key(srcvert[j], j);
@@ -286,7 +357,6 @@ __global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, uint64_t 
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rc->nF[0] = k;
         rc->nF[1] = 0;
-        rc->work[0] = rc->work[1] = 0;
         rc->heavy_n[0] = rc->heavy_n[1] = 0;
         rc->rounds = 0;
     }
@@ -334,7 +404,7 @@ __device__ __forceinline__ int claim_pair_at(uint64_t *T, uint64_t mask, uint32_
 // with the claim itself, and a claim issues the target's label, its first
 // reach-table probe and its offsets together.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_expand(Search S) {
+__device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint32_t nblk) {
     __shared__ uint64_t Qk[kWavesPerBlock][kQcap];   // (vertex, source) keys
     __shared__ int2 Qr[kWavesPerBlock][kQcap];       // (first arc, degree)
     __shared__ int32_t Sx[kWavesPerBlock][4][kWave];
@@ -351,13 +421,12 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
     if (nF == 0) return;
     if (nF > S.fcap) nF = (uint32_t)S.fcap;  // overflow was flagged by ExtractAll
     const int32_t tau = S.tau_from_rc ? (int32_t)ld_relaxed(&rc->tau_cur) : S.tau;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         rc->rounds += 1;
         rc->fdeg = 0;
-        rc->lsdepth = 0;
     }
-    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + wv;
+    const uint32_t nwaves = nblk * kWavesPerBlock;
+    const uint32_t wave_gid = bid * kWavesPerBlock + wv;
     // Seeds per wave: one group per wave when the frontier fits, so a round
     // lasts one local search rather than several in sequence.
     uint32_t G = (uint32_t)S.seeds;
@@ -375,6 +444,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
     uint32_t wseq = 0;
     unsigned long long c_seeds = 0, c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
 
+    // Groups: wave w first takes group w; the groups past the wave count are
+    // dealt out through per-stripe counters (wave w draws from stripe
+    // w % kStripes: group nwaves + stripe + kStripes * draw).
+    const uint32_t wstripe = wave_gid % kStripes;
     uint32_t grp = wave_gid;
     while (grp < ngroups) {
         const uint32_t start = grp * G;
@@ -524,31 +597,66 @@ __global__ __launch_bounds__(kBlock) void k_expand(Search S) {
             c_ins += (unsigned long long)bag_insert_wave(S.bag, h, e, wave_gid, wseq);
         }
         wave_lds_sync();
+        if (ngroups <= nwaves) break;
         uint32_t nxt = 0;
-        if (lane == 0) nxt = atomicAdd(&rc->work[S.par], 1u) + nwaves;
+        if (lane == 0) nxt = nwaves + wstripe + kStripes * atomicAdd(&S.ls->s[wstripe].work[S.par], 1u);
         grp = wave_bcast_u(nxt, 0);
     }
-    if (lane == 0 && depth > 0) atomicMax(&rc->lsdepth, depth);
+    __shared__ uint32_t dmax[kWavesPerBlock];
+    if (lane == 0) dmax[wv] = depth;
     unsigned long long c[kNumCtr] = {c_seeds, c_exp, c_arcs, c_att, c_claims, c_ins};
-    const unsigned long long t = block_flush_ctr(S.cn->c[blockIdx.x % kCtrStripes][S.kind], c);
-    if (threadIdx.x == kCtrClaims && t) atomicAdd(&rc->claims, t);
+    const unsigned long long t = block_flush_ctr(S.cn->c[bid % kCtrStripes][S.kind], c);  // has a barrier
+    StripeLine &sl = S.ls->s[bid % kStripes];
+    if (threadIdx.x == kCtrClaims && t) atomicAdd(&sl.claims, t);
+    if (threadIdx.x == kNumCtr) {
+        uint32_t d = 0;
+        for (int w = 0; w < kWavesPerBlock; w++) d = dmax[w] > d ? dmax[w] : d;
+        if (d) atomicMax(&sl.depth, d);
+    }
+}
+
+// A launch serves one or two search lanes (the forward and the backward
+// search of a batch): with two, the first `split` blocks take lane 0 and the
+// rest lane 1, so the two searches' rounds run side by side.
+struct LanePair {
+    Search S[2];
+    int32_t nl;      // lanes in this launch (1 or 2)
+    uint32_t split;  // blocks of lane 0 when nl == 2
+};
+
+__device__ __forceinline__ int pair_lane(const LanePair &P, uint32_t &bid, uint32_t &nblk) {
+    if (P.nl < 2) return 0;
+    if (bid < P.split) {
+        nblk = P.split;
+        return 0;
+    }
+    bid -= P.split;
+    nblk -= P.split;
+    return 1;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_expand(LanePair P) {
+    uint32_t bid = blockIdx.x, nblk = gridDim.x;
+    const int l = pair_lane(P, bid, nblk);
+    expand_round<MODE>(P.S[l], bid, nblk);
 }
 
 // Edge-parallel expansion of the deferred high-degree entries.  Each item is
 // one kHeavyChunk-arc slice of an adjacency list; a block takes an item and
 // its four waves stride over the slice; claims go to the bag.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_expand_heavy(Search S) {
+__device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint32_t nblk) {
     RoundCtl *rc = S.rc;
     uint32_t nh = ld_relaxed(&rc->heavy_n[S.par]);
     if (nh == 0) return;
     if (nh > S.hcap) nh = (uint32_t)S.hcap;
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
-    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + wv;
+    const uint32_t wave_gid = bid * kWavesPerBlock + wv;
     uint32_t wseq = 0x8000u;
     unsigned long long c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
-    for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    for (uint32_t h = bid; h < nh; h += nblk) {
         const uint64_t e = S.heavy[2 * (uint64_t)h];
         if (e == kEmpty64) continue;  // block-uniform
         const uint32_t chunk = (uint32_t)S.heavy[2 * (uint64_t)h + 1];
@@ -583,8 +691,15 @@ __global__ __launch_bounds__(kBlock) void k_expand_heavy(Search S) {
         }
     }
     unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, c_att, c_claims, c_ins};
-    const unsigned long long t = block_flush_ctr(S.cn->c[blockIdx.x % kCtrStripes][kKindHeavy], c);
-    if (threadIdx.x == kCtrClaims && t) atomicAdd(&rc->claims, t);
+    const unsigned long long t = block_flush_ctr(S.cn->c[bid % kCtrStripes][kKindHeavy], c);
+    if (threadIdx.x == kCtrClaims && t) atomicAdd(&S.ls->s[bid % kStripes].claims, t);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_expand_heavy(LanePair P) {
+    uint32_t bid = blockIdx.x, nblk = gridDim.x;
+    const int l = pair_lane(P, bid, nblk);
+    heavy_round<MODE>(P.S[l], bid, nblk);
 }
 
 // ------------------------------------------------------------ dense mode ----
@@ -596,8 +711,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_heavy(Search S) {
 // vertices, i.e. two bitmap words, so it updates visited/next words with plain
 // stores.  next is written for every word, so it needs no clearing.
 __global__ __launch_bounds__(kBlock) void k_pull(int32_t n, const int32_t *off, const int32_t *adj, uint32_t *vis,
-                                                 const uint32_t *front, uint32_t *next, RoundCtl *rc, Counters *cn,
-                                                 int par) {
+                                                 const uint32_t *front, uint32_t *next, LaneStripes *ls, Counters *cn) {
     const int lane = lane_id();
     uint32_t found_cnt = 0;
     unsigned long long c_exp = 0, c_arcs = 0;
@@ -627,28 +741,41 @@ __global__ __launch_bounds__(kBlock) void k_pull(int32_t n, const int32_t *off, 
             if (bits) vis[wi] = word | bits;
         }
     }
-    block_add_u32(&rc->nF[par ^ 1], found_cnt);
-    // pull claims count as the lane's claims (visited fraction feature)
+    // the next frontier's size and the claims go to the lane's stripes;
+    // k_round_end folds them (pull claims count as the lane's claims)
     unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, 0, (unsigned long long)found_cnt, 0};
     const unsigned long long t = block_flush_ctr(cn->c[blockIdx.x % kCtrStripes][kKindPull], c);
-    if (threadIdx.x == kCtrClaims && t) atomicAdd(&rc->claims, t);
+    StripeLine &sl = ls->s[blockIdx.x % kStripes];
+    if (threadIdx.x == kCtrClaims && t) {
+        atomicAdd(&sl.claims, t);
+        atomicAdd(&sl.nf, (uint32_t)t);
+    }
 }
 
-// Trace mode: snapshot the inputs of the coming round (the policy features).
-__global__ void k_trace_snap(RoundCtl *rc) {
+// Trace mode: snapshot the inputs of the coming round (the policy features);
+// par is the coming round's parity, so the previous round's depth is at par ^ 1.
+__global__ void k_trace_snap(RoundCtl *rc, int par) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         rc->snap_nf = (unsigned long long)rc->nF[0] + rc->nF[1];
         rc->snap_fdeg = rc->fdeg;
         rc->snap_claims = rc->claims;
         rc->snap_rounds = rc->rounds;
-        rc->snap_depth = rc->lsdepth;
+        rc->snap_depth = rc->lsdepth[par ^ 1];
     }
 }
 
-__global__ void k_round_end(RoundCtl *rc, int par) {
+// End of a dense round: the next frontier's size and the claims from the
+// stripes, this round's counters cleared.
+__global__ void k_round_end(RoundCtl *rc, LaneStripes *ls, int par) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t nf = 0;
+        for (int i = 0; i < kStripes; i++) {
+            nf += ls->s[i].nf;
+            ls->s[i].nf = 0;
+        }
+        stripes_fold(rc, ls, par);
+        rc->nF[par ^ 1] = nf;
         rc->nF[par] = 0;
-        rc->work[par] = 0;
         rc->heavy_n[par] = 0;
         rc->rounds += 1;
     }
@@ -713,8 +840,7 @@ __global__ __launch_bounds__(kBlock) void k_bitmap_to_list(int32_t n, const uint
 // S.fdeg_on it also sums the degrees of the extracted entries (the frontier's
 // arc count, used to choose the next round's mode).  The last block to finish
 // resets the bag's chunk state and this round's counters.
-__global__ __launch_bounds__(kBlock) void k_bag_extract(Search S, int par) {
-    __shared__ bool last;
+__device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t bid, uint32_t nblk) {
     __shared__ uint32_t part[kWavesPerBlock];
     __shared__ uint32_t base_s;
     const Bag &B = S.bag;
@@ -725,7 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(Search S, int par) {
     if (r >= B.nchunks) r = B.nchunks - 1;
     const uint64_t nst = bag_chunk_hi(B, r) >> kStripeLog2;
     unsigned long long fdeg = 0;
-    for (uint64_t sb0 = (uint64_t)blockIdx.x * kBlock; sb0 < nst; sb0 += (uint64_t)gridDim.x * kBlock) {
+    for (uint64_t sb0 = (uint64_t)bid * kBlock; sb0 < nst; sb0 += (uint64_t)nblk * kBlock) {
         const uint64_t sb = sb0 + (uint64_t)wv * kWave;
         const uint64_t st = sb + lane;
         uint32_t c = 0;
@@ -764,28 +890,50 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(Search S, int par) {
         }
         if (st < nst && c) B.cnt[st] = 0;
     }
-    if (S.fdeg_on) {
+    if (S.fdeg_on) {  // block-uniform
+        __shared__ unsigned long long fpart[kWavesPerBlock];
         fdeg = wave_sum_u64(fdeg);
-        if (lane == 0 && fdeg) atomicAdd(&rc->fdeg, fdeg);
+        if (lane == 0) fpart[wv] = fdeg;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) t += fpart[w];
+            if (t) atomicAdd(&rc->fdeg, t);
+        }
     }
-    // ExtractAll also clears the chunk state: the last block does it once
-    // every block has finished reading r.
+}
+
+// The reset ExtractAll ends with (one thread, once every block has read r):
+// chunk state and this round's counters.
+__device__ __forceinline__ void extract_reset(const Search &S, int par) {
+    const Bag &B = S.bag;
+    for (uint32_t i = 0; i < B.nchunks && i < (uint32_t)kMaxChunks; i++) B.ctl->sample[i] = 0;
+    B.ctl->r = 0;
+    B.ctl->done_blocks = 0;
+    S.rc->nF[par] = 0;
+    S.rc->heavy_n[par] = 0;
+    stripes_fold(S.rc, S.ls, par);
+}
+
+// ExtractAll of one or two lanes (split as in k_expand); each lane's frontier
+// parity is in its Search.
+__global__ __launch_bounds__(kBlock) void k_bag_extract(LanePair P) {
+    __shared__ bool last;
+    uint32_t bid = blockIdx.x, nblk = gridDim.x;
+    const int l = pair_lane(P, bid, nblk);
+    const Search &S = P.S[l];
+    extract_round(S, S.par, bid, nblk);
+    // ExtractAll also clears the chunk state: the lane's last block does it
+    // once every block of the lane has finished reading r.
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        last = atomicAdd(&B.ctl->done_blocks, 1u) == gridDim.x - 1;
+        last = atomicAdd(&S.bag.ctl->done_blocks, 1u) == nblk - 1;
     }
     __syncthreads();
-    if (last) {
+    if (last && threadIdx.x == 0) {
         __threadfence();
-        for (uint32_t i = threadIdx.x; i < B.nchunks && i < (uint32_t)kMaxChunks; i += blockDim.x) B.ctl->sample[i] = 0;
-        if (threadIdx.x == 0) {
-            B.ctl->r = 0;
-            B.ctl->done_blocks = 0;
-            rc->nF[par] = 0;
-            rc->work[par] = 0;
-            rc->heavy_n[par] = 0;
-        }
+        extract_reset(S, S.par);
     }
 }
 
@@ -794,7 +942,7 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(Search S, int par) {
 // finished with key s; vertices reached one way move to a new subproblem
 // labelled by the hash of (old label, R_in, R_out) (Algorithm 1).
 __global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, const Shared *shc, Perm P, const uint32_t *visF,
-                                const uint32_t *visB, Shared *sh) {
+                                const uint32_t *visB, CountStripes *cs) {
     const int32_t s = single_source(-1, shc, P);
     if (s < 0) return;
     uint32_t cnt = 0;
@@ -809,7 +957,7 @@ __global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, const Shar
             label[v] = relabel_hash(L, b ? sig_term_in(s) : 0ull, f ? sig_term_out(s) : 0ull);
         }
     }
-    block_add_u32(&sh->fin, cnt);
+    block_add_u32(&cs->s[blockIdx.x % kStripes].fin, cnt);
 }
 
 // Multi source, pass 1: accumulate the per-vertex set hashes of R_out (pairs
@@ -839,7 +987,7 @@ __global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, const uint64_t
 // table slot is cleared for the next batch.
 __global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, uint64_t min_, const int32_t *srcvert,
                                 unsigned long long *sig_out, unsigned long long *sig_in, int32_t *fin,
-                                int32_t *stamp, int32_t epoch, int32_t *label, Shared *sh) {
+                                int32_t *stamp, int32_t epoch, int32_t *label, CountStripes *cs) {
     const uint64_t n_out = mout + 1, n_tot = n_out + min_ + 1;
     uint32_t cnt = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_tot; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -860,7 +1008,7 @@ __global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, ui
         sig_out[v] = 0;
         fin[v] = kInf32;
     }
-    block_add_u32(&sh->fin, cnt);
+    block_add_u32(&cs->s[blockIdx.x % kStripes].fin, cnt);
 }
 
 // ---------------------------------------------------------- canonical ----
@@ -901,7 +1049,7 @@ __global__ __launch_bounds__(kBlock) void k_canon_min(int32_t n, const int32_t *
         if (hk[i] >= 0) atomicMin(&aux[hk[i]], hv[i]);
 }
 
-__global__ void k_canon_write(int32_t n, const int32_t *label, const int32_t *aux, int32_t *out, Shared *sh) {
+__global__ void k_canon_write(int32_t n, const int32_t *label, const int32_t *aux, int32_t *out, CountStripes *cs) {
     uint32_t cnt = 0;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t l = label[v];
@@ -909,7 +1057,7 @@ __global__ void k_canon_write(int32_t n, const int32_t *label, const int32_t *au
         out[v] = r;
         cnt += (r == v);
     }
-    block_add_u32(&sh->nscc, cnt);
+    block_add_u32(&cs->s[blockIdx.x % kStripes].nscc, cnt);
 }
 
 // ---------------------------------------------------------- reach output ----
@@ -919,9 +1067,7 @@ __global__ void k_emit_single(int32_t n, const int32_t *label, int32_t L, const 
         const int64_t v = v0 + threadIdx.x;
         const bool hit = v < n && label[v] == L && ((vis[v >> 5] >> (v & 31)) & 1u);
         const uint64_t m = ballot(hit);
-        uint32_t base = 0;
-        if (m && lane_id() == 0) base = atomicAdd(&sh->emit, (uint32_t)popc64(m));
-        base = wave_bcast_u(base, 0);
+        const uint32_t base = block_reserve(&sh->emit, (uint32_t)popc64(m));
         if (hit) {
             const uint64_t pos = (uint64_t)base + rank_below(m);
             if (pos < cap) {
@@ -940,9 +1086,7 @@ __global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, u
         const uint64_t key = i < nt ? T[i] : kEmpty64;
         const bool hit = key != kEmpty64;
         const uint64_t m = ballot(hit);
-        uint32_t base = 0;
-        if (m && lane_id() == 0) base = atomicAdd(&sh->emit, (uint32_t)popc64(m));
-        base = wave_bcast_u(base, 0);
+        const uint32_t base = block_reserve(&sh->emit, (uint32_t)popc64(m));
         if (hit) {
             const uint64_t pos = (uint64_t)base + rank_below(m);
             if (pos < cap) {

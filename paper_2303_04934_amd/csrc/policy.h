@@ -94,11 +94,38 @@ inline void policy_features_host(float nf, float fdeg, float claims, float nsub,
     x[4] = std::log2(1.f + depth);
 }
 
-// Picks the next round's schedule for one search lane: the budget class and
-// frontier mode with the highest predicted rate among the allowed actions
-// (mode_mask bit m allows mode m).  Non-finite scores fall back to the fixed
-// schedule.  Writes the lane's tau_cur / mode_pref (fields given by pointer so
-// that this header does not depend on the round-control layout).
+// Picks the next round's schedule for one search lane from the scores y: the
+// budget class and frontier mode with the highest predicted rate among the
+// allowed actions (mode_mask bit m allows mode m).  Non-finite scores fall
+// back to the fixed schedule.  One thread; writes the lane's tau_cur /
+// mode_pref (fields given by pointer so that this header does not depend on
+// the round-control layout).
+__device__ __forceinline__ void policy_pick(const float *y, uint32_t mode_mask, uint32_t fallback_tau,
+                                            uint32_t *tau_cur, uint32_t *mode_pref, uint32_t *calls,
+                                            uint32_t *fallbacks) {
+    int best = -1;
+    float bv = 0.f;
+    bool ok = true;
+    for (int a = 0; a < kPolicyOut; a++) {
+        if (!isfinite(y[a])) ok = false;
+        if (!((mode_mask >> (a & 1)) & 1u)) continue;
+        if (best < 0 || y[a] > bv) {
+            best = a;
+            bv = y[a];
+        }
+    }
+    *calls += 1;
+    if (!ok || best < 0) {
+        *tau_cur = fallback_tau;
+        *mode_pref = 0;
+        *fallbacks += 1;
+    } else {
+        *tau_cur = policy_tau(best >> 1);
+        *mode_pref = (uint32_t)(best & 1);
+    }
+}
+
+// The policy step before a round, as its own launch (one wave).
 __global__ __launch_bounds__(64) void k_policy_round(const float *W, const uint32_t *nF2, const unsigned long long *fdeg,
                                                      const unsigned long long *claims, const uint32_t *rounds,
                                                      const uint32_t *lsdepth, float nsub, uint32_t mode_mask,
@@ -112,28 +139,7 @@ __global__ __launch_bounds__(64) void k_policy_round(const float *W, const uint3
     __syncthreads();
     policy_forward_wave(W, x, y, h1, h2);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int best = -1;
-        float bv = 0.f;
-        bool ok = true;
-        for (int a = 0; a < kPolicyOut; a++) {
-            if (!isfinite(y[a])) ok = false;
-            if (!((mode_mask >> (a & 1)) & 1u)) continue;
-            if (best < 0 || y[a] > bv) {
-                best = a;
-                bv = y[a];
-            }
-        }
-        *calls += 1;
-        if (!ok || best < 0) {
-            *tau_cur = fallback_tau;
-            *mode_pref = 0;
-            *fallbacks += 1;
-        } else {
-            *tau_cur = policy_tau(best >> 1);
-            *mode_pref = (uint32_t)(best & 1);
-        }
-    }
+    if (threadIdx.x == 0) policy_pick(y, mode_mask, fallback_tau, tau_cur, mode_pref, calls, fallbacks);
 }
 
 inline void policy_release(Policy &p) {

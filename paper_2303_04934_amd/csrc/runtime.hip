@@ -34,7 +34,9 @@ struct DevCtl {
     RoundCtl lane[2];
     BagCtl bag[2];
     Shared sh;
+    CountStripes cs;
     Counters cn;
+    LaneStripes ls[2];
 };
 constexpr size_t kCtlHead = offsetof(DevCtl, cn);
 
@@ -49,6 +51,7 @@ struct Fail {
 };
 
 constexpr int kMaxSlots = 64;   // rounds per launch block
+constexpr int kTimedMax = 2 * kMaxSlots;  // timed launches between host checks (two lanes)
 constexpr int kPhases = 5;      // trim, first, multi, resize, label
 constexpr uint32_t kProbeLimit = 128;
 
@@ -79,9 +82,11 @@ struct scc_ctx {
     bool tables_dirty = false;      // a failed call may leave claims behind
     // options.timing: events around frontier-kernel launches
     bool timing = false;
-    hipEvent_t tev[2][kMaxSlots][2] = {};
-    double tm_ms[3] = {0, 0, 0};
-    int64_t tm_launches[3] = {0, 0, 0};
+    hipEvent_t tev[kTimedMax][2] = {};  // timed launches since the last host check
+    int tev_kind[kTimedMax] = {};
+    int tev_n = 0;
+    double tm_ms[SCC_KERNELS] = {};
+    int64_t tm_launches[SCC_KERNELS] = {};
     int64_t dense_rounds = 0;
     // options.trace rows and the round events that time them
     bool tracing = false;
@@ -179,6 +184,13 @@ void sync_ctl(scc_ctx *c, bool with_counters = false) {
     HIPCHK(hipMemcpyAsync(c->hctl, c->dctl, with_counters ? sizeof(DevCtl) : kCtlHead, hipMemcpyDeviceToHost,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// Sums of the striped call-level counts (host copy, after sync_ctl).
+int64_t count_sum(const scc_ctx *c, uint32_t CountLine::*f) {
+    int64_t t = 0;
+    for (int i = 0; i < kStripes; i++) t += c->hctl->cs.s[i].*f;
+    return t;
 }
 
 // Zeroes the whole control block inside the stream (a fill kernel, no memset).
@@ -301,6 +313,7 @@ Search make_search(scc_ctx *c, int id, const scc_options_t &o, int mode) {
     S.bag.kappa = (uint32_t)o.kappa;
     S.bag.alpha = o.alpha;
     S.rc = &c->dctl->lane[id];
+    S.ls = &c->dctl->ls[id];
     S.cn = &c->dctl->cn;
     S.kind = mode == kMulti ? kKindExpandMulti : kKindExpandSingle;
     S.tau = o.tau;
@@ -323,7 +336,6 @@ struct Lane {
     int64_t rounds = 0;
     // state before the round, for trace rows
     uint64_t fdeg = 0, claims = 0;
-    uint32_t depth = 0;
     uint32_t tau_used = 0;
     int64_t nsub = 1;
     // single source
@@ -354,9 +366,12 @@ void launch_policy(scc_ctx *c, Lane &L, const scc_options_t &o, int dense_opt) {
     Search &S = L.S;
     if (o.policy == 1 && c->policy.loaded) {
         RoundCtl *rc = S.rc;
-        const uint32_t mask = L.mode == kMulti ? 1u : (dense_opt == -1 ? 3u : (dense_opt == 1 ? 2u : 1u));
+        // the policy picks the budget among sparse actions; the frontier mode
+        // stays with the direction rule (dense rounds were too rare in the
+        // training traces to rank them reliably)
+        const uint32_t mask = 1u;
         hipLaunchKernelGGL(k_policy_round, dim3(1), dim3(64), 0, c->stream, c->policy.w, rc->nF, &rc->fdeg, &rc->claims,
-                           &rc->rounds, &rc->lsdepth, (float)L.nsub, mask, (uint32_t)std::max(o.tau, 0), &rc->tau_cur,
+                           &rc->rounds, &rc->lsdepth[L.par ^ 1], (float)L.nsub, mask, (uint32_t)std::max(o.tau, 0), &rc->tau_cur,
                            &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks);
         LAUNCHCHK("k_policy_round");
         S.tau_from_rc = 1;
@@ -367,22 +382,62 @@ void launch_policy(scc_ctx *c, Lane &L, const scc_options_t &o, int dense_opt) {
     }
 }
 
-void launch_sparse(scc_ctx *c, Lane &L, int slot, bool fdeg) {
-    Search &S = L.S;
-    S.par = L.par;
-    S.bag.salt = c->salt++;
-    S.fdeg_on = fdeg ? 1u : 0u;
-    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][slot][0], c->stream));
-    if (L.mode == kMulti) hipLaunchKernelGGL(k_expand<kMulti>, dim3(c->expand_blocks), dim3(kBlock), 0, c->stream, S);
-    else hipLaunchKernelGGL(k_expand<kSingle>, dim3(c->expand_blocks), dim3(kBlock), 0, c->stream, S);
+// options.timing: HIP events around one frontier-kernel launch of `kind`;
+// the host adds them up at its next check (timed_collect).
+int timed_begin(scc_ctx *c, int kind) {
+    if (!c->timing || c->tev_n >= kTimedMax) return -1;
+    const int i = c->tev_n++;
+    c->tev_kind[i] = kind;
+    HIPCHK(hipEventRecord(c->tev[i][0], c->stream));
+    return i;
+}
+void timed_end(scc_ctx *c, int i) {
+    if (i >= 0) HIPCHK(hipEventRecord(c->tev[i][1], c->stream));
+}
+void timed_collect(scc_ctx *c) {
+    for (int i = 0; i < c->tev_n; i++) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->tev[i][0], c->tev[i][1]));
+        c->tm_ms[c->tev_kind[i]] += ms;
+        c->tm_launches[c->tev_kind[i]] += 1;
+    }
+    c->tev_n = 0;
+}
+
+// One sparse round of one or two lanes of the same mode: expand, the
+// edge-parallel pass over deferred heavy entries, and ExtractAll, each one
+// launch for both lanes (the grid split between them).
+void launch_sparse(scc_ctx *c, Lane **ls, int nl, const bool *fdeg) {
+    LanePair P;
+    memset(&P, 0, sizeof P);
+    P.nl = nl;
+    const unsigned eb = (unsigned)c->expand_blocks;
+    const unsigned hb = (unsigned)c->num_cu * 4;
+    const unsigned xb = extract_blocks(c) * (unsigned)nl;
+    for (int j = 0; j < nl; j++) {
+        Search &S = ls[j]->S;
+        S.par = ls[j]->par;
+        S.bag.salt = c->salt++;
+        S.fdeg_on = fdeg[j] ? 1u : 0u;
+        const unsigned mine = nl == 2 ? (j == 0 ? eb / 2 : eb - eb / 2) : eb;
+        S.vgc_cut = mine * (uint32_t)kWavesPerBlock;
+        P.S[j] = S;
+    }
+    const int mode = ls[0]->mode;
+    P.split = eb / 2;
+    const int t = timed_begin(c, P.S[0].kind);
+    if (mode == kMulti) hipLaunchKernelGGL(k_expand<kMulti>, dim3(eb), dim3(kBlock), 0, c->stream, P);
+    else hipLaunchKernelGGL(k_expand<kSingle>, dim3(eb), dim3(kBlock), 0, c->stream, P);
     LAUNCHCHK("k_expand");
-    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][slot][1], c->stream));
-    if (L.mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, S);
-    else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, S);
+    timed_end(c, t);
+    P.split = hb / 2;
+    if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     LAUNCHCHK("k_expand_heavy");
-    hipLaunchKernelGGL(k_bag_extract, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, S, L.par);
+    P.split = xb / 2;
+    hipLaunchKernelGGL(k_bag_extract, dim3(xb), dim3(kBlock), 0, c->stream, P);
     LAUNCHCHK("k_bag_extract");
-    L.par ^= 1;
+    for (int j = 0; j < nl; j++) ls[j]->par ^= 1;
 }
 
 void launch_dense(scc_ctx *c, Lane &L) {
@@ -397,12 +452,12 @@ void launch_dense(scc_ctx *c, Lane &L) {
         LAUNCHCHK("k_list_to_bitmap");
         L.have_list = false;
     }
-    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][0][0], c->stream));
+    const int t = timed_begin(c, kKindPull);
     hipLaunchKernelGGL(k_pull, dim3(grid_for(c, (uint64_t)L.n)), dim3(kBlock), 0, c->stream, L.n, L.roff, L.radj, S.vis,
-                       front, next, S.rc, S.cn, L.par);
+                       front, next, S.ls, S.cn);
     LAUNCHCHK("k_pull");
-    if (c->timing) HIPCHK(hipEventRecord(c->tev[L.id][0][1], c->stream));
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, c->stream, S.rc, L.par);
+    timed_end(c, t);
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, c->stream, S.rc, S.ls, L.par);
     LAUNCHCHK("k_round_end");
     std::swap(c->bm[L.id][0], c->bm[L.id][1]);
     L.par ^= 1;
@@ -430,7 +485,7 @@ void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
     S.tmask = ts - 1;
     L.S = S;
     hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)P.n)), dim3(kBlock), 0, c->stream, c->srcvert.p,
-                       &c->dctl->sh, S.table, S.tmask, kProbeLimit, S.F, S.rc);
+                       &c->dctl->sh, S.table, S.tmask, kProbeLimit, S.F, S.rc, S.ls);
     LAUNCHCHK("k_seed_multi");
     L.par = 0;
     L.nf = 1;
@@ -461,7 +516,6 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
         L.dense = dense_opt == 1 && L.mode == kSingle;
         L.have_list = true;
         L.fdeg = L.claims = 0;
-        L.depth = 0;
         L.rounds = 0;
         L.nsub = std::max<int64_t>(P.nsub, 1);
     }
@@ -487,42 +541,50 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
         }
         if (!any) break;
         const int k = (watch || c->tracing) ? 1 : K;
-        for (int r = 0; r < k; r++)
+        for (int r = 0; r < k; r++) {
+            // sparse lanes of this round share their launches (traced rounds
+            // are timed per lane, so they launch alone)
+            Lane *sp[2];
+            bool sp_fdeg[2];
+            int nsp = 0;
             for (int i = 0; i < nl; i++) {
                 Lane &L = lanes[i];
                 if (!L.live) continue;
                 if (c->tracing) {
-                    hipLaunchKernelGGL(k_trace_snap, dim3(1), dim3(64), 0, c->stream, L.S.rc);
+                    hipLaunchKernelGGL(k_trace_snap, dim3(1), dim3(64), 0, c->stream, L.S.rc, L.par);
                     LAUNCHCHK("k_trace_snap");
                 }
                 launch_policy(c, L, o, dense_opt);
                 if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][0], c->stream));
                 was_dense[L.id] = L.dense;
+                const bool fd = fdeg_always || (watch && L.mode == kSingle && dense_opt != 0);
                 if (L.dense) {
                     launch_dense(c, L);
                     c->dense_rounds++;
+                } else if (c->tracing) {
+                    Lane *one = &L;
+                    launch_sparse(c, &one, 1, &fd);
                 } else {
-                    launch_sparse(c, L, r, fdeg_always || (watch && L.mode == kSingle && dense_opt != 0));
+                    sp[nsp] = &L;
+                    sp_fdeg[nsp++] = fd;
                 }
                 if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][1], c->stream));
             }
+            if (nsp == 2 && sp[0]->mode != sp[1]->mode) {
+                launch_sparse(c, &sp[0], 1, &sp_fdeg[0]);
+                launch_sparse(c, &sp[1], 1, &sp_fdeg[1]);
+            } else if (nsp) {
+                launch_sparse(c, sp, nsp, sp_fdeg);
+            }
+        }
         launched += (uint64_t)k;
         sync_ctl(c);
+        timed_collect(c);
         bool switched = false;
         for (int i = 0; i < nl; i++) {
             Lane &L = lanes[i];
             if (!L.live) continue;
             const RoundCtl &rc = c->hctl->lane[L.id];
-            if (c->timing) {
-                const int nslots = L.dense ? 1 : k;
-                const int kind = L.dense ? (int)kKindPull : L.S.kind;
-                for (int s = 0; s < nslots; s++) {
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, c->tev[L.id][s][0], c->tev[L.id][s][1]));
-                    c->tm_ms[kind] += ms;
-                }
-                c->tm_launches[kind] += nslots;
-            }
             if ((rc.err & kErrCapacity) || c->hctl->bag[L.id].overflow) {
                 set_err(c, "frontier capacity exceeded (err=%u, bag overflow=%u)", rc.err, c->hctl->bag[L.id].overflow);
                 throw Fail{SCC_EINTERNAL};
@@ -544,14 +606,13 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 if (P.st) P.st->rounds_multi += rc.rounds;  // rounds of the abandoned attempt
                 restart_multi(c, L, P);
                 L.fdeg = L.claims = 0;
-                L.depth = 0;
                 L.rounds = 0;
                 continue;
             }
             L.fdeg = rc.fdeg;
             L.claims = rc.claims;
-            L.depth = rc.lsdepth;
-            if (L.nf > 0 && nf_new > 0) L.growth = std::pow((double)nf_new / (double)L.nf, 1.0 / (double)(L.dense ? 1 : k));
+            if (L.nf > 0 && nf_new > 0)
+                L.growth = std::pow((double)nf_new / (double)L.nf, 1.0 / (double)(L.dense ? 1 : k));
             L.nf = nf_new;
             L.rounds = rc.rounds;
             if (L.nf == 0) {
@@ -561,10 +622,12 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
             L.par = rc.nF[0] ? 0 : 1;
             if (L.mode != kSingle || dense_opt == 0) continue;
             bool to_dense, to_sparse;
-            if (use_policy && dense_opt == -1) {
-                // the policy's preferred mode for the next round
-                to_dense = !L.dense && rc.mode_pref == 1;
-                to_sparse = L.dense && rc.mode_pref == 0;
+            if (o.policy == 2 && dense_opt == -1 && c->tracing) {
+                // exploration: a coin decides the mode once the frontier is not tiny
+                c->explore_state = mix64(c->explore_state + 0x632BE59BD9B4E019ull);
+                const bool want_dense = (int64_t)L.nf * 256 > L.nsub && (c->explore_state >> 63);
+                to_dense = !L.dense && want_dense;
+                to_sparse = L.dense && !want_dense;
             } else {
                 to_dense = !L.dense && (dense_opt == 1 || (watch && rc.fdeg > arcs_on));
                 to_sparse = L.dense && dense_opt == -1 && (int64_t)L.nf < back_off;
@@ -666,11 +729,11 @@ void init_call(scc_ctx *c, scc_stats_t *st, int64_t n, int64_t m, const scc_opti
     HIPCHK(hipSetDevice(c->device));
     c->err.clear();
     c->timing = o && o->timing;
-    if (c->timing && !c->tev[0][0][0])
+    if (c->timing && !c->tev[0][0])
         for (auto &a : c->tev)
-            for (auto &b : a)
-                for (auto &e : b) HIPCHK(hipEventCreate(&e));
-    for (int i = 0; i < 3; i++) {
+            for (auto &e : a) HIPCHK(hipEventCreate(&e));
+    c->tev_n = 0;
+    for (int i = 0; i < SCC_KERNELS; i++) {
         c->tm_ms[i] = 0;
         c->tm_launches[i] = 0;
     }
@@ -744,11 +807,11 @@ void fill_counters(scc_ctx *c, scc_stats_t *st, int64_t n) {
     st->claim_attempts = sum(kCtrAttempts);
     st->claims = sum(kCtrClaims);
     st->bag_inserts = sum(kCtrInserts);
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < SCC_KERNELS; k++) {
         st->ms_kernel[k] = c->tm_ms[k];
         st->launches_kernel[k] = c->tm_launches[k];
     }
-    for (int k = 0; k < 2; k++)
+    for (int k : {kKindExpandSingle, kKindExpandMulti})
         st->bytes_kernel[k] = (int64_t)(ctr_kind(cn, k, kCtrSeeds) * 8 + ctr_kind(cn, k, kCtrExpanded) * 8 +
                                         ctr_kind(cn, k, kCtrArcs) * 4 + ctr_kind(cn, k, kCtrAttempts) * 4 +
                                         ctr_kind(cn, k, kCtrClaims) * (k == kKindExpandMulti ? 8 : 4) +
@@ -785,7 +848,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     phase_begin(c, 0, ph);
     Shared *sh = &c->dctl->sh;
     hipLaunchKernelGGL(k_trim, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g.out_off, g.in_off,
-                       c->label.p, o.trim ? 1 : 0, sh);
+                       c->label.p, o.trim ? 1 : 0, &c->dctl->cs);
     LAUNCHCHK("k_trim");
     Perm P;
     P.n = (uint32_t)n;
@@ -814,7 +877,8 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p, 0, -1,
                            sh, P, c->vis[d].p);
         LAUNCHCHK("k_premark");
-        hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, -1, sh, P, c->F[d].p, &c->dctl->lane[d]);
+        hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, -1, sh, P, c->F[d].p, &c->dctl->lane[d],
+                           &c->dctl->ls[d]);
         LAUNCHCHK("k_seed_single");
         L[d].id = d;
         L[d].mode = kSingle;
@@ -839,10 +903,10 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     if (st) st->rounds_first = L[0].rounds + L[1].rounds;
     phase_end(c, ph);
     const uint32_t j1 = c->hctl->sh.first;
-    const int64_t trimmed = c->hctl->sh.trimmed;
+    const int64_t trimmed = count_sum(c, &CountLine::trimmed);
     phase_begin(c, 4, ph);
     hipLaunchKernelGGL(k_finish_single, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p, 0,
-                       sh, P, c->vis[0].p, c->vis[1].p, sh);
+                       sh, P, c->vis[0].p, c->vis[1].p, &c->dctl->cs);
     LAUNCHCHK("k_finish_single");
     phase_end(c, ph);
     if (st && j1 < (uint32_t)n) st->batches = 1;
@@ -905,7 +969,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             L[d].S.table = T.p;
             L[d].S.tmask = ts - 1;
             hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, kmax)), dim3(kBlock), 0, c->stream, c->srcvert.p, sh, T.p,
-                               ts - 1, kProbeLimit, c->F[d].p, &c->dctl->lane[d]);
+                               ts - 1, kProbeLimit, c->F[d].p, &c->dctl->lane[d], &c->dctl->ls[d]);
             LAUNCHCHK("k_seed_multi");
         }
         DP.nsub = active;
@@ -915,7 +979,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         const uint32_t k = c->hctl->sh.k;
         a_out = c->hctl->lane[0].claims + k;
         a_in = c->hctl->lane[1].claims + k;
-        active = (int64_t)n - trimmed - (int64_t)c->hctl->sh.fin;
+        active = (int64_t)n - trimmed - count_sum(c, &CountLine::fin);
         if (k == 0) continue;  // nothing was claimed; the tables are still clean
         if (st) {
             st->batches += 1;
@@ -928,7 +992,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         LAUNCHCHK("k_accumulate");
         hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
                            c->Tin.p, ts_in - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p, c->stamp.p, epoch,
-                           c->label.p, sh);
+                           c->label.p, &c->dctl->cs);
         LAUNCHCHK("k_relabel_multi");
         phase_end(c, ph);
         epoch++;
@@ -941,14 +1005,13 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
                        c->aux.p, &sh->bad);
     LAUNCHCHK("k_canon_min");
     hipLaunchKernelGGL(k_canon_write, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p,
-                       c->aux.p, labels_out, sh);
+                       c->aux.p, labels_out, &c->dctl->cs);
     LAUNCHCHK("k_canon_write");
     phase_end(c, ph);
     sync_ctl(c, st != nullptr);
-    if ((c->hctl->sh.bad & kErrUnfinished) ||
-        (int64_t)c->hctl->sh.fin + (int64_t)c->hctl->sh.trimmed != (int64_t)n) {
-        set_err(c, "internal: %lld of %d vertices ended without an SCC key",
-                (long long)((int64_t)n - c->hctl->sh.fin - c->hctl->sh.trimmed), n);
+    const int64_t fin_all = count_sum(c, &CountLine::fin) + count_sum(c, &CountLine::trimmed);
+    if ((c->hctl->sh.bad & kErrUnfinished) || fin_all != (int64_t)n) {
+        set_err(c, "internal: %lld of %d vertices ended without an SCC key", (long long)((int64_t)n - fin_all), n);
         throw Fail{SCC_EINTERNAL};
     }
     if (st) {
@@ -959,8 +1022,8 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         st->ms_multi += ms[2];
         st->ms_resize += resize_ms;
         st->ms_label += ms[4];
-        st->trimmed = c->hctl->sh.trimmed;
-        st->n_scc = c->hctl->sh.nscc;
+        st->trimmed = count_sum(c, &CountLine::trimmed);
+        st->n_scc = count_sum(c, &CountLine::nscc);
         st->dense_rounds = c->dense_rounds;
         fill_counters(c, st, n);
     }
@@ -1150,9 +1213,8 @@ void scc_destroy(scc_ctx_t *c) {
     if (c->dctl) (void)hipFree(c->dctl);
     if (c->hctl) (void)hipHostFree(c->hctl);
     for (auto &a : c->tev)
-        for (auto &b : a)
-            for (auto &e : b)
-                if (e) (void)hipEventDestroy(e);
+        for (auto &e : a)
+            if (e) (void)hipEventDestroy(e);
     for (auto e : c->pev) (void)hipEventDestroy(e);
     for (auto &a : c->rev)
         for (auto &e : a)
@@ -1236,7 +1298,8 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
             Perm P0{(uint32_t)n, 1, 0};
             hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, labels, lab, s,
                                sh, P0, c->vis[0].p);
-            hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, s, sh, P0, c->F[0].p, &c->dctl->lane[0]);
+            hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, s, sh, P0, c->F[0].p, &c->dctl->lane[0],
+                               &c->dctl->ls[0]);
             LAUNCHCHK("k_seed_single");
             L.mode = kSingle;
             L.S = make_search(c, 0, o, kSingle);
@@ -1261,7 +1324,7 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
             ensure_lane(c, 0, std::max<uint64_t>(ts, (uint64_t)n), (uint32_t)o.lambda_log2);
             reset_bag(c, 0);
             hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)k)), dim3(kBlock), 0, c->stream, c->srcvert.p, sh,
-                               c->Tout.p, ts - 1, kProbeLimit, c->F[0].p, &c->dctl->lane[0]);
+                               c->Tout.p, ts - 1, kProbeLimit, c->F[0].p, &c->dctl->lane[0], &c->dctl->ls[0]);
             LAUNCHCHK("k_seed_multi");
             L.mode = kMulti;
             L.T = &c->Tout;
@@ -1437,7 +1500,12 @@ scc_status scc_bag_selftest(scc_ctx_t *c, const uint64_t *keys, int64_t n, int32
             adv += c->hctl->bag[0].advances;
             if (c->hctl->bag[0].overflow) { set_err(c, "bag overflow"); throw Fail{SCC_EINTERNAL}; }
             // par = 1: ExtractAll appends to nF[0], which accumulates over rounds
-            hipLaunchKernelGGL(k_bag_extract, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, S, 1);
+            LanePair LP;
+            memset(&LP, 0, sizeof LP);
+            LP.S[0] = S;
+            LP.S[0].par = 1;
+            LP.nl = 1;
+            hipLaunchKernelGGL(k_bag_extract, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, LP);
             LAUNCHCHK("k_bag_extract");
             fill_u32(c, &c->dctl->bag[0].advances, 1, 0u);
         }

@@ -35,13 +35,37 @@ def test_library_exports_every_declared_symbol():
     assert lib.scc_version().startswith(b"hipscc")
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-def test_struct_layouts_match_header():
-    # the Python mirrors must have the sizes the C compiler gives the structs
+def _c_layout(tmp_path, fields):
+    """sizeof / offsetof of header structs as the C compiler lays them out."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "hipscc.h"', "int main(void) {"]
+    for struct, members in fields.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (struct, struct))
+        for f in members:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (struct, f, struct, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    return {k: int(v) for k, v in (ln.split() for ln in out if ln)}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the Python mirrors must have the sizes and offsets the C compiler gives
     from paper_2303_04934_amd import _native
-    assert ctypes.sizeof(_native.Graph) == 8 + 4 * 8
-    assert ctypes.sizeof(_native.Options) == 4 * 6 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4 * 5
-    assert ctypes.sizeof(_native.Stats) == 6 * 8 + 18 * 8 + 3 * 8 * 3 + 3 * 8
+    mirrors = {"scc_graph_t": _native.Graph, "scc_options_t": _native.Options, "scc_stats_t": _native.Stats}
+    fields = {k: [f for f, _ in v._fields_] for k, v in mirrors.items()}
+    c = _c_layout(tmp_path, fields)
+    for struct, py in mirrors.items():
+        assert ctypes.sizeof(py) == c[struct], struct
+        for f in fields[struct]:
+            assert getattr(py, f).offset == c["%s.%s" % (struct, f)], (struct, f)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
