@@ -61,12 +61,18 @@ typedef struct {
 /* Tunables.  Fill with scc_default_options() and change fields; passing NULL
  * means the defaults.  None of them changes a result, only work and rounds.
  *   tau          VGC budget: arcs a local search examines before it stops and
- *                hands its queue to the next frontier (Section 3.2; default
- *                512).  tau <= 1 disables local search (plain frontier BFS,
+ *                hands its queue to the next frontier (Section 3.2).  Default
+ *                2048: Section 3.2 ties the budget to the cost of scheduling a
+ *                task, and a GPU round (launches plus host check) costs more
+ *                than a multicore one, so the default sits above the paper's
+ *                2^9, inside the range it finds insensitive (2^6..2^12).
+ *                tau <= 1 disables local search (plain frontier BFS,
  *                Algorithm 2).
  *   beta         prefix-doubling multiplier for the source batches
  *                (Algorithm 1; Table 1 uses 1.5).  Must be > 1.
- *   lambda_log2  log2 of the hash bag's first chunk (Table 1: 10).
+ *   lambda_log2  log2 of the hash bag's first chunk (Table 1: 10 for tens of
+ *                threads).  0 (default) = automatic: up to 2^20 slots, so that
+ *                thousands of inserting wavefronts spread over many stripes.
  *   sigma        samples that trigger a hash bag chunk advance (Table 1: 50).
  *   kappa        stripe probes before an insert forces a chunk advance.
  *   alpha        target load factor of a bag chunk (0 < alpha < 1).
@@ -83,11 +89,21 @@ typedef struct {
  *                two); 0 = the sizing heuristic of Section 4.5.
  *   seeds_per_wave frontier entries a wavefront takes per fetch (1..64);
  *                0 = chosen from the frontier size.
- *   timing       1 = bracket every launch of the frontier-expansion kernel
- *                with HIP events and report its time and algorithmic bytes
- *                in the stats (costs a little launch overhead).
+ *   timing       bit mask over SCC_KERNEL_*: bit k brackets every launch of
+ *                frontier kernel k with HIP events and reports its time and
+ *                algorithmic bytes in the stats (each timed launch costs a
+ *                little overhead, so time only what is needed; 0 = off).
  *   trace        1 = record one row per search round (read back with
- *                scc_trace_read); the host then checks every round. */
+ *                scc_trace_read); the host then checks every round.
+ *   arcs_per_lane  arcs each lane of a wavefront has in flight per pass of
+ *                a local-search step: 1, 2 or 4 (0 = default 1).  More arcs
+ *                per lane shorten the chain of dependent memory accesses of a
+ *                step but cost registers, hence resident wavefronts.
+ *   vgc_fill     local search runs in rounds whose frontier has fewer arcs
+ *                (entries x average degree) than vgc_fill x the lanes of the
+ *                expand grid; a frontier above that keeps the GPU busy on its
+ *                own and runs as a plain round (0 = default 2; < 0 = cut at
+ *                one entry per wavefront). */
 typedef struct {
     int32_t tau;
     float beta;
@@ -104,14 +120,19 @@ typedef struct {
     int32_t seeds_per_wave;
     int32_t timing;
     int32_t trace;
-    int32_t reserved[5];
+    int32_t arcs_per_lane;
+    float vgc_fill;
+    int32_t reserved[3];
 } scc_options_t;
 
 /* Frontier kernels timed with options.timing. */
 #define SCC_KERNEL_EXPAND_SINGLE 0  /* sparse single-source expand round */
 #define SCC_KERNEL_EXPAND_MULTI 1   /* multi-source expand round */
 #define SCC_KERNEL_PULL 2           /* dense pull round */
-#define SCC_KERNELS 3
+#define SCC_KERNEL_HEAVY_SINGLE 3   /* edge-parallel pass, single-source lanes */
+#define SCC_KERNEL_HEAVY_MULTI 4    /* edge-parallel pass, multi-source lanes */
+#define SCC_KERNEL_EXTRACT 5        /* ExtractAll */
+#define SCC_KERNELS 6
 
 /* Per-call statistics (host struct, written when non-NULL).  Times are
  * milliseconds measured with HIP events on the context's stream.  The five
@@ -139,15 +160,15 @@ typedef struct {
     int64_t bytes_alg;        /* algorithmic HBM bytes of the whole call */
     /* with options.timing: for the frontier kernels (SCC_KERNEL_*) the summed
      * event time of their launches, the number of launches and their
-     * algorithmic bytes.  Expand: frontier entry 8, offsets 8 per expanded
-     * entry, 4 per scanned arc, 4 per claim attempt, 8 (multi) or 4 (single)
-     * per claim, 8 per bag insert.  Pull: visited and
+     * algorithmic bytes.  Expand and edge-parallel: frontier entry 8,
+     * offsets 8 per expanded entry, 4 per scanned arc, 4 per claim attempt,
+     * 8 (multi) or 4 (single) per claim, 8 per bag insert.  Pull: visited and
      * next words (n/4), offsets 8 per unvisited vertex, 8 per scanned arc
-     * (target id + frontier word). */
+     * (target id + frontier word).  ExtractAll: 24 per extracted entry (bag
+     * slot read, frontier write, the entry's offsets for the degree sum). */
     double ms_kernel[SCC_KERNELS];
     int64_t launches_kernel[SCC_KERNELS];
     int64_t bytes_kernel[SCC_KERNELS];
-    int64_t reserved[3];
 } scc_stats_t;
 
 /* Library version string (static storage). */

@@ -21,7 +21,7 @@ class Graph(ctypes.Structure):
 
 
 # frontier kernels timed with options.timing (SCC_KERNEL_* in hipscc.h)
-KERNEL_NAMES = ["k_expand<0>", "k_expand<1>", "k_pull"]
+KERNEL_NAMES = ["k_expand<0, 1>", "k_expand<1, 1>", "k_pull", "k_expand_heavy<0>", "k_expand_heavy<1>", "k_bag_extract"]
 KERNELS = len(KERNEL_NAMES)
 
 
@@ -31,7 +31,7 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("policy", ctypes.c_int32), ("dense", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("trim", ctypes.c_int32), ("table_init", ctypes.c_int64),
                 ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("trace", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -42,7 +42,7 @@ class Stats(ctypes.Structure):
                                                "bag_inserts", "bag_chunk_advances", "table_restarts", "trimmed",
                                                "n_scc", "policy_calls", "policy_fallbacks", "bytes_alg")] + \
                [("ms_kernel", ctypes.c_double * KERNELS), ("launches_kernel", ctypes.c_int64 * KERNELS),
-                ("bytes_kernel", ctypes.c_int64 * KERNELS), ("reserved", ctypes.c_int64 * 3)]
+                ("bytes_kernel", ctypes.c_int64 * KERNELS)]
 
     def as_dict(self):
         d = {}

@@ -120,4 +120,23 @@ __host__ __device__ __forceinline__ uint32_t perm_apply(const Perm &P, uint32_t 
     return x;
 }
 
+// Inverse of perm_apply: the Feistel rounds undone in reverse order, walking
+// the cycle back until the value is below n.
+__host__ __device__ __forceinline__ uint32_t perm_invert(const Perm &P, uint32_t y) {
+    const uint32_t hb = P.half_bits, hm = (1u << hb) - 1u;
+    do {
+        uint32_t L = y >> hb, R = y & hm;
+#pragma unroll
+        for (int r = 3; r >= 0; r--) {
+            // forward round r mapped (L, R) to (R, L ^ F(R, r))
+            const uint32_t F = (uint32_t)mix64(((uint64_t)L << 8 | (uint64_t)r) ^ P.key) & hm;
+            const uint32_t t = R ^ F;
+            R = L;
+            L = t;
+        }
+        y = (L << hb) | R;
+    } while (y >= P.n);
+    return y;
+}
+
 }  // namespace hipscc

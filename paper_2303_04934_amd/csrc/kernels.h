@@ -10,7 +10,7 @@ enum { kCtrSeeds = 0, kCtrExpanded, kCtrArcs, kCtrAttempts, kCtrClaims, kCtrInse
 constexpr int kCtrStripes = 32;
 // counter kinds: expand single-source, expand multi-source, pull, edge-parallel
 // Counter kinds: the work of each frontier kernel.
-enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavy = 3, kNumKinds = 4 };
+enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavySingle = 3, kKindHeavyMulti = 4, kNumKinds = 5 };
 
 // Round control of one search lane (one direction of a search), in device
 // memory.  Rounds alternate between parity 0 and 1 so that one round's
@@ -22,7 +22,7 @@ struct RoundCtl {
     uint32_t rounds;       // rounds with a non-empty frontier
     uint32_t listpos;      // bitmap -> list conversion cursor
     uint32_t pad;
-    unsigned long long fdeg;    // summed degree of the frontier ExtractAll produced
+    unsigned long long fdeg[2]; // summed degree of the frontier of each parity (0: not known)
     unsigned long long claims;  // pairs (or vertices) claimed by this lane's search (folded at round end)
     uint32_t lsdepth[2];        // deepest local search (steps) of the round of each parity (folded)
     uint32_t tau_cur;           // VGC budget of the next round when a policy sets it
@@ -132,11 +132,11 @@ struct Search {
     Counters *cn;
     int32_t kind;           // counter kind of the expand kernel
     int32_t par;
-    uint32_t fdeg_on;       // ExtractAll also sums the degrees of the new frontier
     int32_t tau;            // <= 1: plain frontier BFS
     int32_t seeds;          // 0: automatic
     int32_t heavy_deg;
-    uint32_t vgc_cut;       // rounds whose frontier has at least this many entries skip local search
+    uint32_t vgc_cut;       // local search only while the frontier has fewer entries than this ...
+    unsigned long long vgc_arcs;  // ... or, when its degree sum is known, fewer arcs than this
     uint32_t tau_from_rc;   // 1: the budget of each round is rc->tau_cur (set by the policy)
 };
 
@@ -246,6 +246,34 @@ __global__ void k_first_active(Perm P, uint32_t p0, uint32_t p1, const int32_t *
     }
 }
 
+// The same selection for a long range, by a coalesced scan over the vertices:
+// an active vertex is a source when its permutation position (perm_invert)
+// falls in [p0, p1).  Reading every label in order costs 4n bytes, less than
+// gathering the range's labels in random order once the range exceeds about
+// n/16 positions (one cache sector per position).
+__global__ void k_select_scan(Perm P, uint32_t p0, uint32_t p1, int32_t n, const int32_t *label, int32_t *srcvert,
+                              int32_t *srclab, Shared *sh) {
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        int32_t l = -1;
+        if (v < n) {
+            l = label[v];
+            if (l >= 0) {
+                const uint32_t j = perm_invert(P, (uint32_t)v);
+                if (j < p0 || j >= p1) l = -1;
+            }
+        }
+        const bool act = l >= 0;
+        const uint64_t m = ballot(act);
+        const uint32_t base = block_reserve(&sh->k, (uint32_t)popc64(m));
+        if (act) {
+            const uint32_t idx = base + rank_below(m);
+            srcvert[idx] = (int32_t)v;
+            srclab[idx] = l;
+        }
+    }
+}
+
 // Sources of one batch: the active vertices among permutation positions
 // [p0, p1) (Algorithm 1: F = P_i intersect V').
 __global__ void k_select_sources(Perm P, uint32_t p0, uint32_t p1, const int32_t *label, int32_t *srcvert,
@@ -338,6 +366,7 @@ __global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_
         rc->nF[0] = s >= 0 ? 1u : 0u;
         rc->nF[1] = 0;
         rc->heavy_n[0] = rc->heavy_n[1] = 0;
+        rc->fdeg[0] = rc->fdeg[1] = 0;
         rc->claims = 0;
         rc->rounds = 0;
         rc->err = 0;
@@ -345,73 +374,81 @@ __global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_
 }
 
 // Multi-source seed: claim (s_j, j) and put it in the frontier.
-__global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, uint64_t *T, uint64_t mask, uint32_t limit,
-                             uint64_t *F, RoundCtl *rc, LaneStripes *ls) {
-    if (blockIdx.x == 0) stripes_clear(ls);
+// Multi-source seed of one or two lanes (blockIdx.y = lane): claim (s_j, j)
+// in the lane's reach table and put it in its frontier.
+struct SeedArgs {
+    uint64_t *T[2];
+    uint64_t mask[2];
+    uint64_t *F[2];
+    RoundCtl *rc[2];
+    LaneStripes *ls[2];
+};
+
+__global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, SeedArgs A, uint32_t limit) {
+    const int l = blockIdx.y;
+    RoundCtl *rc = A.rc[l];
+    if (blockIdx.x == 0) stripes_clear(A.ls[l]);
     const uint32_t k = sh->k;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
         uint64_t key = pair_key(srcvert[j], j);
-        if (claim_pair(T, mask, limit, key) < 0) atomicOr(&rc->err, kErrTable);
-        F[j] = key;
+        if (claim_pair(A.T[l], A.mask[l], limit, key) < 0) atomicOr(&rc->err, kErrTable);
+        A.F[l][j] = key;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rc->nF[0] = k;
         rc->nF[1] = 0;
         rc->heavy_n[0] = rc->heavy_n[1] = 0;
+        rc->fdeg[0] = rc->fdeg[1] = 0;
         rc->rounds = 0;
     }
 }
 
-// ---------------------------------------------------------------- expand ----
-// Reach-table claim that starts from an already loaded first probe: slot h
-// held `cur`.  1: new pair claimed; 0: already present; -1: probe limit hit.
-__device__ __forceinline__ int claim_pair_at(uint64_t *T, uint64_t mask, uint32_t limit, uint64_t key, uint64_t h,
-                                             uint64_t cur) {
-    for (uint32_t p = 0; p <= limit; p++) {
-        if (p > 0) cur = ld_relaxed64(T + h);
-        if (cur == key) return 0;
-        if (cur == kEmpty64) {
-            const unsigned long long old = atomicCAS((unsigned long long *)(T + h), (unsigned long long)kEmpty64,
-                                                     (unsigned long long)key);
-            if (old == kEmpty64) return 1;
-            if (old == key) return 0;
-        }
-        h = (h + 1) & mask;
+// Start of a multi-source batch: both lanes' round state and the batch's
+// source count back to zero (one small launch).
+__global__ void k_batch_reset(Shared *sh, RoundCtl *rc0, RoundCtl *rc1) {
+    uint32_t *a = reinterpret_cast<uint32_t *>(rc0);
+    uint32_t *b = reinterpret_cast<uint32_t *>(rc1);
+    for (uint32_t i = threadIdx.x; i < sizeof(RoundCtl) / 4; i += blockDim.x) {
+        a[i] = 0u;
+        b[i] = 0u;
     }
-    return -1;
+    if (threadIdx.x == 0) sh->k = 0;
 }
 
+// ---------------------------------------------------------------- expand ----
 // One frontier round with vertical granularity control (Section 3.1-3.2).
 //
-// Each wavefront takes a group of frontier entries and runs one bounded local
-// search seeded with all of them: its FIFO local queue lives in LDS; each step
-// the wave takes whole entries from the queue head (as many as fit in
-// kStepArcs arcs), spreads their arcs over its 64 lanes, and claims the
-// targets.  Every examined arc counts against the budget tau * (seeds), as in
-// Section 3.2 (successful or not).  Newly claimed entries go to the local
-// queue while it has room, otherwise straight to the hash bag.  When the
-// budget is spent or the queue is empty, what is left in the queue is
-// inserted into the bag, i.e. the next frontier (Section 3.2).  With tau <= 1,
-// or when the frontier alone fills every wavefront, nothing is searched
-// locally and this is one plain round (Algorithm 2/3).  Entries with more than
-// heavy_deg arcs are deferred to k_expand_heavy, which spreads one adjacency
-// list over the whole grid (Section 3.2: vertices with more than tau
-// neighbours are processed edge-parallel).
+// Each wavefront is one task: it takes a group of frontier entries and runs
+// one bounded local search seeded with all of them.  Its FIFO local queue
+// lives in LDS; each step the wave takes whole entries from the queue head
+// (as many as fit in kStepArcs arcs), spreads their arcs over its 64 lanes,
+// and claims the targets.  Every examined arc counts against the task's
+// budget tau, successful or not (Section 3.2).  Newly claimed entries go to
+// the local queue while it has room, otherwise straight to the hash bag.
+// When the budget is spent or the queue is empty, what is left in the queue
+// is inserted into the bag, i.e. the next frontier (Section 3.2).  With
+// tau <= 1, or when the frontier's arcs already keep every lane busy, nothing
+// is searched locally and this is one plain round (Algorithm 2/3).  Entries
+// with more than heavy_deg arcs are deferred to k_expand_heavy, which spreads
+// one adjacency list over the whole grid (Section 3.2: vertices with more
+// than tau neighbours are processed edge-parallel).
 //
 // A local search is a chain of dependent memory accesses, one level per step,
 // so its latency is the critical path of a round.  Queue entries therefore
-// carry their adjacency range, fetched when the entry is claimed in parallel
-// with the claim itself, and a claim issues the target's label, its first
-// reach-table probe and its offsets together.
-template <int MODE>
+// carry their adjacency range and label, fetched when the entry is claimed
+// in parallel with the claim itself, and a claim issues the target's label,
+// its first reach-table probe and its offsets together.
+template <int MODE, int ILP>
 __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint32_t nblk) {
-    __shared__ uint64_t Qk[kWavesPerBlock][kQcap];   // (vertex, source) keys
-    __shared__ int2 Qr[kWavesPerBlock][kQcap];       // (first arc, degree)
+    __shared__ uint64_t Qk[kWavesPerBlock][kQcap];                      // (vertex, source) keys
+    __shared__ int2 Qr[kWavesPerBlock][kQcap];                          // (first arc, degree)
+    __shared__ int32_t Ql[kWavesPerBlock][MODE == kMulti ? kQcap : 1];  // entry's label (kMulti)
     __shared__ int32_t Sx[kWavesPerBlock][4][kWave];
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
     uint64_t *Q = Qk[wv];
     int2 *R = Qr[wv];
+    int32_t *QL = Ql[wv];
     int32_t *sexcl = Sx[wv][0];
     int32_t *sbeg = Sx[wv][1];
     int32_t *ssrc = Sx[wv][2];
@@ -421,10 +458,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
     if (nF == 0) return;
     if (nF > S.fcap) nF = (uint32_t)S.fcap;  // overflow was flagged by ExtractAll
     const int32_t tau = S.tau_from_rc ? (int32_t)ld_relaxed(&rc->tau_cur) : S.tau;
-    if (bid == 0 && threadIdx.x == 0) {
-        rc->rounds += 1;
-        rc->fdeg = 0;
-    }
+    if (bid == 0 && threadIdx.x == 0) rc->rounds += 1;
     const uint32_t nwaves = nblk * kWavesPerBlock;
     const uint32_t wave_gid = bid * kWavesPerBlock + wv;
     // Seeds per wave: one group per wave when the frontier fits, so a round
@@ -439,7 +473,8 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
     // Local search exists to give each task enough work when the frontier is
     // too small to keep the machine busy (Section 3.1); a frontier that
     // already fills every wavefront runs as a plain round.
-    const bool vgc = tau > 1 && nF < S.vgc_cut;
+    const unsigned long long fd = ld_relaxed64(reinterpret_cast<const uint64_t *>(&rc->fdeg[S.par]));
+    const bool vgc = tau > 1 && ((fd > 0 && S.vgc_arcs > 0) ? fd < S.vgc_arcs : nF < S.vgc_cut);
     uint32_t depth = 0;
     uint32_t wseq = 0;
     unsigned long long c_seeds = 0, c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
@@ -458,11 +493,16 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
             const int32_t b0 = S.off[u];
             Q[lane] = e;
             R[lane] = make_int2(b0, S.off[u + 1] - b0);
+            // an entry (u, j) was claimed because label[u] equals source j's
+            // label, so the entry carries the label its arcs are tested against
+            if (MODE == kMulti) QL[lane] = S.label[u];
         }
         c_seeds += (unsigned long long)cnt;
         int head = 0, tail = cnt;
         long long t = 0;
-        const long long budget = vgc ? (long long)tau * cnt : 0;
+        // the wave is the task whose size tau bounds (Section 3.2): its
+        // seeds share one local search of budget tau
+        const long long budget = vgc ? (long long)tau : 0;
         wave_lds_sync();
         uint32_t steps = 0;
         while (head < tail && (!vgc || t < budget)) {
@@ -478,7 +518,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                 beg = r2.x;
                 d = r2.y;
                 s = key_source(e);
-                if (MODE == kMulti) lab = S.srclab[s];
+                if (MODE == kMulti) lab = QL[(head + lane) & kQmask];
             }
             // candidate heavy entries (deferred to the edge-parallel kernel)
             bool hv = lane < k && d > S.heavy_deg;
@@ -528,64 +568,167 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
             t += D;
             c_exp += (mine && !hv) ? 1 : 0;
             wave_lds_sync();
-            for (int base = 0; base < D; base += kWave) {
-                const int a = base + lane;
-                bool claimed = false;
-                uint64_t ne = 0;
-                int2 nr = make_int2(0, 0);
-                if (a < D) {
-                    int lo = 0, hi = kk - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (sexcl[mid] <= a) lo = mid; else hi = mid - 1;
+            // The step's arcs, ILP per lane: every phase issues the memory
+            // operations of all of a lane's arcs before it uses any result,
+            // so a step costs one chain of dependent accesses, not ILP.
+            for (int base = 0; base < D; base += kWave * ILP) {
+                bool va[ILP], claimed[ILP];
+                int32_t w[ILP], lo_[ILP];
+                uint64_t ne[ILP];
+                int2 nr[ILP];
+                int32_t nlab[ILP];
+#pragma unroll
+                for (int j = 0; j < ILP; j++) {
+                    const int a = base + j * kWave + lane;
+                    va[j] = a < D;
+                    claimed[j] = false;
+                    ne[j] = 0;
+                    nr[j] = make_int2(0, 0);
+                    nlab[j] = 0;
+                    int lo = 0;
+                    if (va[j]) {
+                        int hi = kk - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (sexcl[mid] <= a) lo = mid; else hi = mid - 1;
+                        }
                     }
-                    const int32_t w = S.adj[sbeg[lo] + (a - sexcl[lo])];
-                    const uint32_t src = (uint32_t)ssrc[lo];
-                    ne = pair_key(w, src);
-                    c_arcs++;
-                    if (MODE == kSingle) {
-                        c_att++;
-                        const uint32_t bit = 1u << (w & 31);
-                        uint32_t *word = S.vis + (w >> 5);
-                        if (vgc) {
-                            // latency-bound regime: one atomic, offsets fetched alongside
-                            const int32_t o0 = S.off[w], o1 = S.off[w + 1];
-                            claimed = (atomicOr(word, bit) & bit) == 0;
-                            nr = make_int2(o0, o1 - o0);
-                        } else {
-                            // throughput regime: skip the atomic for visited targets
-                            claimed = !(ld_relaxed(word) & bit) && (atomicOr(word, bit) & bit) == 0;
+                    lo_[j] = lo;
+                    w[j] = 0;
+                    if (va[j]) w[j] = S.adj[sbeg[lo] + (a - sexcl[lo])];
+                }
+#pragma unroll
+                for (int j = 0; j < ILP; j++)
+                    if (va[j]) {
+                        ne[j] = pair_key(w[j], (uint32_t)ssrc[lo_[j]]);
+                        c_arcs++;
+                    }
+                if (MODE == kSingle) {
+                    uint32_t old[ILP];
+                    int32_t o0[ILP], o1[ILP];
+                    if (vgc) {
+                        // latency-bound regime: one atomic, offsets fetched alongside
+#pragma unroll
+                        for (int j = 0; j < ILP; j++) {
+                            old[j] = 0xffffffffu;
+                            o0[j] = o1[j] = 0;
+                            if (va[j]) {
+                                o0[j] = S.off[w[j]];
+                                o1[j] = S.off[w[j] + 1];
+                                old[j] = atomicOr(S.vis + (w[j] >> 5), 1u << (w[j] & 31));
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < ILP; j++) {
+                            claimed[j] = va[j] && !((old[j] >> (w[j] & 31)) & 1u);
+                            nr[j] = make_int2(o0[j], o1[j] - o0[j]);
                         }
                     } else {
-                        const uint64_t h = mix64(ne) & S.tmask;
-                        const int32_t lw = S.label[w];
-                        const uint64_t t0 = ld_relaxed64(S.table + h);
-                        int32_t o0 = 0, o1 = 0;
-                        if (vgc) {
-                            o0 = S.off[w];
-                            o1 = S.off[w + 1];
-                        }
-                        if (lw == slab[lo]) {
-                            c_att++;
-                            const int c = claim_pair_at(S.table, S.tmask, S.probe_limit, ne, h, t0);
-                            if (c < 0) atomicOr(&rc->err, kErrTable);
-                            claimed = c == 1;
-                        }
-                        nr = make_int2(o0, o1 - o0);
+                        // throughput regime: skip the atomic for visited targets
+#pragma unroll
+                        for (int j = 0; j < ILP; j++) old[j] = va[j] ? ld_relaxed(S.vis + (w[j] >> 5)) : 0xffffffffu;
+#pragma unroll
+                        for (int j = 0; j < ILP; j++)
+                            if (!((old[j] >> (w[j] & 31)) & 1u)) old[j] = atomicOr(S.vis + (w[j] >> 5), 1u << (w[j] & 31));
+                            else old[j] = 0xffffffffu;
+#pragma unroll
+                        for (int j = 0; j < ILP; j++) claimed[j] = va[j] && !((old[j] >> (w[j] & 31)) & 1u);
                     }
+#pragma unroll
+                    for (int j = 0; j < ILP; j++) c_att += va[j] ? 1 : 0;
+                } else {
+                    uint64_t h[ILP], cur[ILP];
+                    int32_t o0[ILP], o1[ILP];
+                    int st[ILP];  // 2: claim pending, 1: claimed, 0: present or skipped
+#pragma unroll
+                    for (int j = 0; j < ILP; j++) {
+                        h[j] = 0;
+                        cur[j] = 0;
+                        o0[j] = o1[j] = 0;
+                        nlab[j] = -1;
+                        if (va[j]) {
+                            h[j] = mix64(ne[j]) & S.tmask;
+                            nlab[j] = S.label[w[j]];
+                            cur[j] = ld_relaxed64(S.table + h[j]);
+                            if (vgc) {
+                                o0[j] = S.off[w[j]];
+                                o1[j] = S.off[w[j] + 1];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < ILP; j++) {
+                        st[j] = (va[j] && nlab[j] == slab[lo_[j]]) ? 2 : 0;
+                        c_att += st[j] == 2 ? 1 : 0;
+                        nr[j] = make_int2(o0[j], o1[j] - o0[j]);
+                    }
+                    // linear probing from the first slot (already loaded);
+                    // every round of the loop is one load + one CAS per lane
+                    for (uint32_t p = 0;; p++) {
+                        unsigned long long old[ILP];
+                        bool cas[ILP];
+#pragma unroll
+                        for (int j = 0; j < ILP; j++) {
+                            cas[j] = false;
+                            old[j] = 0;
+                            if (st[j] == 2) {
+                                if (cur[j] == ne[j]) {
+                                    st[j] = 0;
+                                } else if (cur[j] == kEmpty64) {
+                                    old[j] = atomicCAS((unsigned long long *)(S.table + h[j]),
+                                                       (unsigned long long)kEmpty64, (unsigned long long)ne[j]);
+                                    cas[j] = true;
+                                }
+                            }
+                        }
+                        bool more = false;
+#pragma unroll
+                        for (int j = 0; j < ILP; j++) {
+                            if (cas[j] && old[j] == kEmpty64) st[j] = 1;
+                            else if (cas[j] && old[j] == ne[j]) st[j] = 0;
+                            if (st[j] == 2) {
+                                h[j] = (h[j] + 1) & S.tmask;
+                                more = true;
+                            }
+                        }
+                        if (!more) break;
+                        if (p >= S.probe_limit) {
+#pragma unroll
+                            for (int j = 0; j < ILP; j++) st[j] = st[j] == 2 ? 0 : st[j];
+                            atomicOr(&rc->err, kErrTable);
+                            break;
+                        }
+#pragma unroll
+                        for (int j = 0; j < ILP; j++)
+                            if (st[j] == 2) cur[j] = ld_relaxed64(S.table + h[j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < ILP; j++) claimed[j] = st[j] == 1;
                 }
-                const uint64_t cmask = ballot(claimed);
-                if (cmask == 0) continue;
-                const int nc = popc64(cmask);
-                c_claims += claimed ? 1 : 0;
+                // new entries: the local queue while it has room, else the bag
+                int tot = 0, rk[ILP];
+#pragma unroll
+                for (int j = 0; j < ILP; j++) {
+                    const uint64_t m = ballot(claimed[j]);
+                    rk[j] = tot + rank_below(m);
+                    tot += popc64(m);
+                    c_claims += claimed[j] ? 1 : 0;
+                }
+                if (tot == 0) continue;
                 const int room = vgc ? kQcap - (tail - head) : 0;
-                const int r = rank_below(cmask);
-                if (claimed && r < room) {
-                    Q[(tail + r) & kQmask] = ne;
-                    R[(tail + r) & kQmask] = nr;
+                bool tobag[ILP];
+#pragma unroll
+                for (int j = 0; j < ILP; j++) {
+                    if (claimed[j] && rk[j] < room) {
+                        const int qi = (tail + rk[j]) & kQmask;
+                        Q[qi] = ne[j];
+                        R[qi] = nr[j];
+                        if (MODE == kMulti) QL[qi] = nlab[j];
+                    }
+                    tobag[j] = claimed[j] && rk[j] >= room;
                 }
-                tail += nc < room ? nc : room;
-                c_ins += (unsigned long long)bag_insert_wave(S.bag, claimed && r >= room, ne, wave_gid, wseq);
+                tail += tot < room ? tot : room;
+                c_ins += (unsigned long long)bag_insert_wave_n<ILP>(S.bag, tobag, ne, wave_gid, wseq);
             }
             wave_lds_sync();
         }
@@ -635,11 +778,11 @@ __device__ __forceinline__ int pair_lane(const LanePair &P, uint32_t &bid, uint3
     return 1;
 }
 
-template <int MODE>
+template <int MODE, int ILP>
 __global__ __launch_bounds__(kBlock) void k_expand(LanePair P) {
     uint32_t bid = blockIdx.x, nblk = gridDim.x;
     const int l = pair_lane(P, bid, nblk);
-    expand_round<MODE>(P.S[l], bid, nblk);
+    expand_round<MODE, ILP>(P.S[l], bid, nblk);
 }
 
 // Edge-parallel expansion of the deferred high-degree entries.  Each item is
@@ -691,7 +834,8 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
         }
     }
     unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, c_att, c_claims, c_ins};
-    const unsigned long long t = block_flush_ctr(S.cn->c[bid % kCtrStripes][kKindHeavy], c);
+    const unsigned long long t =
+        block_flush_ctr(S.cn->c[bid % kCtrStripes][MODE == kMulti ? kKindHeavyMulti : kKindHeavySingle], c);
     if (threadIdx.x == kCtrClaims && t) atomicAdd(&S.ls->s[bid % kStripes].claims, t);
 }
 
@@ -757,7 +901,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(int32_t n, const int32_t *off, 
 __global__ void k_trace_snap(RoundCtl *rc, int par) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         rc->snap_nf = (unsigned long long)rc->nF[0] + rc->nF[1];
-        rc->snap_fdeg = rc->fdeg;
+        rc->snap_fdeg = rc->fdeg[par];
         rc->snap_claims = rc->claims;
         rc->snap_rounds = rc->rounds;
         rc->snap_depth = rc->lsdepth[par ^ 1];
@@ -776,6 +920,7 @@ __global__ void k_round_end(RoundCtl *rc, LaneStripes *ls, int par) {
         stripes_fold(rc, ls, par);
         rc->nF[par ^ 1] = nf;
         rc->nF[par] = 0;
+        rc->fdeg[0] = rc->fdeg[1] = 0;  // a pull round does not sum degrees
         rc->heavy_n[par] = 0;
         rc->rounds += 1;
     }
@@ -882,7 +1027,7 @@ __device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t
                 const uint64_t v = B.slots[((sb + j) << kStripeLog2) + lane];
                 if (oj + lane < S.fcap) S.F[oj + lane] = v;
                 else atomicOr(&rc->err, kErrCapacity);
-                if (S.fdeg_on) {
+                if (S.off) {  // the bag self-test extracts keys of no graph
                     const int32_t u = key_vertex(v);
                     fdeg += (unsigned long long)(S.off[u + 1] - S.off[u]);
                 }
@@ -890,7 +1035,9 @@ __device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t
         }
         if (st < nst && c) B.cnt[st] = 0;
     }
-    if (S.fdeg_on) {  // block-uniform
+    {
+        // the new frontier's degree sum (its offsets are read anyway by the
+        // next round, so this mostly warms the cache for it)
         __shared__ unsigned long long fpart[kWavesPerBlock];
         fdeg = wave_sum_u64(fdeg);
         if (lane == 0) fpart[wv] = fdeg;
@@ -898,7 +1045,7 @@ __device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t
         if (threadIdx.x == 0) {
             unsigned long long t = 0;
             for (int w = 0; w < kWavesPerBlock; w++) t += fpart[w];
-            if (t) atomicAdd(&rc->fdeg, t);
+            if (t) atomicAdd(&rc->fdeg[par ^ 1], t);
         }
     }
 }
@@ -911,6 +1058,7 @@ __device__ __forceinline__ void extract_reset(const Search &S, int par) {
     B.ctl->r = 0;
     B.ctl->done_blocks = 0;
     S.rc->nF[par] = 0;
+    S.rc->fdeg[par] = 0;
     S.rc->heavy_n[par] = 0;
     stripes_fold(S.rc, S.ls, par);
 }

@@ -51,7 +51,7 @@ struct Fail {
 };
 
 constexpr int kMaxSlots = 64;   // rounds per launch block
-constexpr int kTimedMax = 2 * kMaxSlots;  // timed launches between host checks (two lanes)
+constexpr int kTimedMax = 4 * kMaxSlots;  // timed launches between host checks
 constexpr int kPhases = 5;      // trim, first, multi, resize, label
 constexpr uint32_t kProbeLimit = 128;
 
@@ -63,6 +63,9 @@ struct scc_ctx {
     bool own_stream = false;
     int num_cu = 256;
     int expand_blocks = 2048;
+    int expand_grid[2][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
+    int arcs_per_lane = 1;          // options.arcs_per_lane of the current call
+    double vgc_fill = 2.0;          // options.vgc_fill of the current call
     std::string err;
 
     DevBuf<int32_t> label, aux, stamp, srcvert, srclab, fin;
@@ -81,7 +84,7 @@ struct scc_ctx {
     uint32_t salt = 1;
     bool tables_dirty = false;      // a failed call may leave claims behind
     // options.timing: events around frontier-kernel launches
-    bool timing = false;
+    uint32_t timing = 0;            // options.timing: bit k times kernel k (SCC_KERNEL_*)
     hipEvent_t tev[kTimedMax][2] = {};  // timed launches since the last host check
     int tev_kind[kTimedMax] = {};
     int tev_n = 0;
@@ -235,9 +238,9 @@ void phase_collect(scc_ctx *c, double *ms) {
 scc_options_t defaults() {
     scc_options_t o;
     memset(&o, 0, sizeof o);
-    o.tau = 512;
+    o.tau = 2048;
     o.beta = 1.5f;
-    o.lambda_log2 = 10;
+    o.lambda_log2 = 0;
     o.sigma = 50;
     o.kappa = 8;
     o.alpha = 0.5f;
@@ -252,10 +255,27 @@ scc_options_t defaults() {
     return o;
 }
 
+// log2 of the hash bag's first chunk for searches of up to `entries` entries
+// per round.  options.lambda_log2 = 0 picks it: every wavefront that inserts
+// reserves room in one random 64-slot stripe of the current chunk, so the
+// first chunk needs many stripes to keep thousands of wavefronts' atomics
+// apart: 2^20 slots, or less for small searches (at least 2^10, the paper's
+// value for tens of threads).
+uint32_t lam_log2_for(const scc_options_t &o, uint64_t entries) {
+    if (o.lambda_log2 > 0) return (uint32_t)o.lambda_log2;
+    uint32_t l = 10;
+    while (l < 20 && (1ull << l) < entries) l++;
+    return l;
+}
+
 void check_opts(scc_ctx *c, const scc_options_t &o) {
+    if (o.arcs_per_lane != 0 && o.arcs_per_lane != 1 && o.arcs_per_lane != 2 && o.arcs_per_lane != 4) {
+        set_err(c, "arcs_per_lane must be 0, 1, 2 or 4");
+        throw Fail{SCC_EINVAL};
+    }
     if (!(o.beta > 1.0f) || !(o.beta < 1e6f)) { set_err(c, "beta must be > 1"); throw Fail{SCC_EINVAL}; }
-    if (o.lambda_log2 < kStripeLog2 || o.lambda_log2 > 24) {
-        set_err(c, "lambda_log2 must be in [%d, 24]", kStripeLog2);
+    if (o.lambda_log2 != 0 && (o.lambda_log2 < kStripeLog2 || o.lambda_log2 > 24)) {
+        set_err(c, "lambda_log2 must be 0 (automatic) or in [%d, 24]", kStripeLog2);
         throw Fail{SCC_EINVAL};
     }
     if (o.sigma < 1 || o.kappa < 0 || !(o.alpha > 0.f && o.alpha < 1.f)) {
@@ -338,6 +358,7 @@ struct Lane {
     uint64_t fdeg = 0, claims = 0;
     uint32_t tau_used = 0;
     int64_t nsub = 1;
+    double avg_deg = 1.0;    // arcs per vertex of the graph (local-search cut)
     // single source
     bool dense = false, have_list = true;
     const int32_t *roff = nullptr, *radj = nullptr;
@@ -370,7 +391,7 @@ void launch_policy(scc_ctx *c, Lane &L, const scc_options_t &o, int dense_opt) {
         // stays with the direction rule (dense rounds were too rare in the
         // training traces to rank them reliably)
         const uint32_t mask = 1u;
-        hipLaunchKernelGGL(k_policy_round, dim3(1), dim3(64), 0, c->stream, c->policy.w, rc->nF, &rc->fdeg, &rc->claims,
+        hipLaunchKernelGGL(k_policy_round, dim3(1), dim3(64), 0, c->stream, c->policy.w, rc->nF, &rc->fdeg[L.par], &rc->claims,
                            &rc->rounds, &rc->lsdepth[L.par ^ 1], (float)L.nsub, mask, (uint32_t)std::max(o.tau, 0), &rc->tau_cur,
                            &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks);
         LAUNCHCHK("k_policy_round");
@@ -385,7 +406,7 @@ void launch_policy(scc_ctx *c, Lane &L, const scc_options_t &o, int dense_opt) {
 // options.timing: HIP events around one frontier-kernel launch of `kind`;
 // the host adds them up at its next check (timed_collect).
 int timed_begin(scc_ctx *c, int kind) {
-    if (!c->timing || c->tev_n >= kTimedMax) return -1;
+    if (!((c->timing >> kind) & 1) || c->tev_n >= kTimedMax) return -1;
     const int i = c->tev_n++;
     c->tev_kind[i] = kind;
     HIPCHK(hipEventRecord(c->tev[i][0], c->stream));
@@ -404,39 +425,59 @@ void timed_collect(scc_ctx *c) {
     c->tev_n = 0;
 }
 
+// The expand kernel of a search mode and arcs-per-lane setting.
+const void *expand_kernel(int mode, int apl) {
+    if (mode == kMulti) {
+        if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kMulti, 1>);
+        if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kMulti, 2>);
+        return reinterpret_cast<const void *>(&k_expand<kMulti, 4>);
+    }
+    if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kSingle, 1>);
+    if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kSingle, 2>);
+    return reinterpret_cast<const void *>(&k_expand<kSingle, 4>);
+}
+
 // One sparse round of one or two lanes of the same mode: expand, the
 // edge-parallel pass over deferred heavy entries, and ExtractAll, each one
 // launch for both lanes (the grid split between them).
-void launch_sparse(scc_ctx *c, Lane **ls, int nl, const bool *fdeg) {
+void launch_sparse(scc_ctx *c, Lane **ls, int nl) {
     LanePair P;
     memset(&P, 0, sizeof P);
     P.nl = nl;
-    const unsigned eb = (unsigned)c->expand_blocks;
+    const int mode = ls[0]->mode;
+    const int ai = c->arcs_per_lane == 1 ? 0 : (c->arcs_per_lane == 2 ? 1 : 2);
+    const unsigned eb = (unsigned)c->expand_grid[mode][ai];
     const unsigned hb = (unsigned)c->num_cu * 4;
     const unsigned xb = extract_blocks(c) * (unsigned)nl;
     for (int j = 0; j < nl; j++) {
         Search &S = ls[j]->S;
         S.par = ls[j]->par;
         S.bag.salt = c->salt++;
-        S.fdeg_on = fdeg[j] ? 1u : 0u;
         const unsigned mine = nl == 2 ? (j == 0 ? eb / 2 : eb - eb / 2) : eb;
-        S.vgc_cut = mine * (uint32_t)kWavesPerBlock;
+        // local search while the frontier's arcs leave the lanes short of work
+        const double waves = (double)mine * kWavesPerBlock;
+        const double arcs = c->vgc_fill > 0 ? c->vgc_fill * (double)mine * kBlock : 0.0;
+        S.vgc_cut = (uint32_t)std::min(std::max(waves, arcs / ls[j]->avg_deg), 2147483647.0);
+        S.vgc_arcs = c->vgc_fill > 0 ? (unsigned long long)arcs : 0ull;
         P.S[j] = S;
     }
-    const int mode = ls[0]->mode;
     P.split = eb / 2;
     const int t = timed_begin(c, P.S[0].kind);
-    if (mode == kMulti) hipLaunchKernelGGL(k_expand<kMulti>, dim3(eb), dim3(kBlock), 0, c->stream, P);
-    else hipLaunchKernelGGL(k_expand<kSingle>, dim3(eb), dim3(kBlock), 0, c->stream, P);
-    LAUNCHCHK("k_expand");
+    const void *fn = expand_kernel(mode, c->arcs_per_lane);
+    void *args[] = {&P};
+    HIPCHK(hipLaunchKernel(fn, dim3(eb), dim3(kBlock), args, 0, c->stream));
     timed_end(c, t);
     P.split = hb / 2;
+    const int th = timed_begin(c, mode == kMulti ? SCC_KERNEL_HEAVY_MULTI : SCC_KERNEL_HEAVY_SINGLE);
     if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     LAUNCHCHK("k_expand_heavy");
+    timed_end(c, th);
     P.split = xb / 2;
+    const int tx = timed_begin(c, SCC_KERNEL_EXTRACT);
     hipLaunchKernelGGL(k_bag_extract, dim3(xb), dim3(kBlock), 0, c->stream, P);
     LAUNCHCHK("k_bag_extract");
+    timed_end(c, tx);
     for (int j = 0; j < nl; j++) ls[j]->par ^= 1;
 }
 
@@ -484,8 +525,15 @@ void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
     S.table = L.T->p;
     S.tmask = ts - 1;
     L.S = S;
-    hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)P.n)), dim3(kBlock), 0, c->stream, c->srcvert.p,
-                       &c->dctl->sh, S.table, S.tmask, kProbeLimit, S.F, S.rc, S.ls);
+    SeedArgs A;
+    memset(&A, 0, sizeof A);
+    A.T[0] = S.table;
+    A.mask[0] = S.tmask;
+    A.F[0] = S.F;
+    A.rc[0] = S.rc;
+    A.ls[0] = S.ls;
+    hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)P.n), 1), dim3(kBlock), 0, c->stream, c->srcvert.p,
+                       &c->dctl->sh, A, kProbeLimit);
     LAUNCHCHK("k_seed_multi");
     L.par = 0;
     L.nf = 1;
@@ -506,7 +554,6 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
     const scc_options_t &o = *P.o;
     const int dense_opt = o.dense;
     const bool use_policy = o.policy == 1 && c->policy.loaded;
-    const bool fdeg_always = use_policy || c->tracing;
     for (int i = 0; i < nl; i++) {
         Lane &L = lanes[i];
         L.live = true;
@@ -518,10 +565,18 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
         L.fdeg = L.claims = 0;
         L.rounds = 0;
         L.nsub = std::max<int64_t>(P.nsub, 1);
+        L.avg_deg = P.n > 0 ? std::max(1.0, (double)P.m / (double)P.n) : 1.0;
     }
     const uint64_t arcs_on = (uint64_t)std::max<int64_t>(P.m / 14, 1);
     const int64_t back_off = std::max<int64_t>(P.nsub / 24, 1);
-    int K = 1;
+    // rounds between host checks: they double while nothing needs watching.
+    // Multi-source searches start at 2, which saves a check on the many
+    // two-round searches of low-diameter graphs (a spare round on an empty
+    // frontier is a few microseconds of empty launches); single-source
+    // searches start at 1 so that the dense switch is seen in time.
+    bool all_multi = true;
+    for (int i = 0; i < nl; i++) all_multi = all_multi && lanes[i].mode == kMulti;
+    int K = all_multi ? 2 : 1;
     uint64_t launched = 0;
     uint64_t limit = (uint64_t)P.n + 64;
     for (int i = 0; i < nl; i++)
@@ -545,7 +600,6 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
             // sparse lanes of this round share their launches (traced rounds
             // are timed per lane, so they launch alone)
             Lane *sp[2];
-            bool sp_fdeg[2];
             int nsp = 0;
             for (int i = 0; i < nl; i++) {
                 Lane &L = lanes[i];
@@ -557,24 +611,22 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 launch_policy(c, L, o, dense_opt);
                 if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][0], c->stream));
                 was_dense[L.id] = L.dense;
-                const bool fd = fdeg_always || (watch && L.mode == kSingle && dense_opt != 0);
                 if (L.dense) {
                     launch_dense(c, L);
                     c->dense_rounds++;
                 } else if (c->tracing) {
                     Lane *one = &L;
-                    launch_sparse(c, &one, 1, &fd);
+                    launch_sparse(c, &one, 1);
                 } else {
-                    sp[nsp] = &L;
-                    sp_fdeg[nsp++] = fd;
+                    sp[nsp++] = &L;
                 }
                 if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][1], c->stream));
             }
             if (nsp == 2 && sp[0]->mode != sp[1]->mode) {
-                launch_sparse(c, &sp[0], 1, &sp_fdeg[0]);
-                launch_sparse(c, &sp[1], 1, &sp_fdeg[1]);
+                launch_sparse(c, &sp[0], 1);
+                launch_sparse(c, &sp[1], 1);
             } else if (nsp) {
-                launch_sparse(c, sp, nsp, sp_fdeg);
+                launch_sparse(c, sp, nsp);
             }
         }
         launched += (uint64_t)k;
@@ -609,7 +661,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 L.rounds = 0;
                 continue;
             }
-            L.fdeg = rc.fdeg;
+            L.fdeg = rc.fdeg[rc.nF[0] ? 0 : 1];
             L.claims = rc.claims;
             if (L.nf > 0 && nf_new > 0)
                 L.growth = std::pow((double)nf_new / (double)L.nf, 1.0 / (double)(L.dense ? 1 : k));
@@ -629,7 +681,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 to_dense = !L.dense && want_dense;
                 to_sparse = L.dense && !want_dense;
             } else {
-                to_dense = !L.dense && (dense_opt == 1 || (watch && rc.fdeg > arcs_on));
+                to_dense = !L.dense && (dense_opt == 1 || L.fdeg > arcs_on);
                 to_sparse = L.dense && dense_opt == -1 && (int64_t)L.nf < back_off;
             }
             if (to_dense) {
@@ -728,7 +780,9 @@ void validate_graph(scc_ctx *c, const GraphDev &g) {
 void init_call(scc_ctx *c, scc_stats_t *st, int64_t n, int64_t m, const scc_options_t *o = nullptr) {
     HIPCHK(hipSetDevice(c->device));
     c->err.clear();
-    c->timing = o && o->timing;
+    c->timing = o ? (uint32_t)o->timing : 0u;
+    c->arcs_per_lane = (o && o->arcs_per_lane > 0) ? o->arcs_per_lane : 1;
+    c->vgc_fill = (o && o->vgc_fill != 0.f) ? (double)o->vgc_fill : 2.0;
     if (c->timing && !c->tev[0][0])
         for (auto &a : c->tev)
             for (auto &e : a) HIPCHK(hipEventCreate(&e));
@@ -811,11 +865,19 @@ void fill_counters(scc_ctx *c, scc_stats_t *st, int64_t n) {
         st->ms_kernel[k] = c->tm_ms[k];
         st->launches_kernel[k] = c->tm_launches[k];
     }
-    for (int k : {kKindExpandSingle, kKindExpandMulti})
-        st->bytes_kernel[k] = (int64_t)(ctr_kind(cn, k, kCtrSeeds) * 8 + ctr_kind(cn, k, kCtrExpanded) * 8 +
-                                        ctr_kind(cn, k, kCtrArcs) * 4 + ctr_kind(cn, k, kCtrAttempts) * 4 +
-                                        ctr_kind(cn, k, kCtrClaims) * (k == kKindExpandMulti ? 8 : 4) +
-                                        ctr_kind(cn, k, kCtrInserts) * 8);
+    auto search_bytes = [&](int k, bool multi) {
+        return (int64_t)(ctr_kind(cn, k, kCtrSeeds) * 8 + ctr_kind(cn, k, kCtrExpanded) * 8 +
+                         ctr_kind(cn, k, kCtrArcs) * 4 + ctr_kind(cn, k, kCtrAttempts) * 4 +
+                         ctr_kind(cn, k, kCtrClaims) * (multi ? 8 : 4) + ctr_kind(cn, k, kCtrInserts) * 8);
+    };
+    st->bytes_kernel[SCC_KERNEL_EXPAND_SINGLE] = search_bytes(kKindExpandSingle, false);
+    st->bytes_kernel[SCC_KERNEL_EXPAND_MULTI] = search_bytes(kKindExpandMulti, true);
+    st->bytes_kernel[SCC_KERNEL_HEAVY_SINGLE] = search_bytes(kKindHeavySingle, false);
+    st->bytes_kernel[SCC_KERNEL_HEAVY_MULTI] = search_bytes(kKindHeavyMulti, true);
+    // every sparse-round insert is extracted once
+    st->bytes_kernel[SCC_KERNEL_EXTRACT] =
+        (int64_t)(ctr_kind(cn, kKindExpandSingle, kCtrInserts) + ctr_kind(cn, kKindExpandMulti, kCtrInserts) +
+                  ctr_kind(cn, kKindHeavySingle, kCtrInserts) + ctr_kind(cn, kKindHeavyMulti, kCtrInserts)) * 24;
     st->bytes_kernel[2] = (int64_t)(ctr_kind(cn, kKindPull, kCtrExpanded) * 8 + ctr_kind(cn, kKindPull, kCtrArcs) * 8) +
                           c->dense_rounds * (n / 4);
     // whole call: searches (expand, edge-parallel, pull), bag traffic
@@ -839,7 +901,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     fill_u64(c, (uint64_t *)c->sig_out.p, (uint64_t)n, 0ull);
     fill_u64(c, (uint64_t *)c->sig_in.p, (uint64_t)n, 0ull);
     for (int i = 0; i < 2; i++) {
-        ensure_lane(c, i, (uint64_t)n, (uint32_t)o.lambda_log2);
+        ensure_lane(c, i, (uint64_t)n, lam_log2_for(o, (uint64_t)n));
         reset_bag(c, i);
     }
     phase_end(c, ph);
@@ -925,10 +987,17 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         const uint64_t p1 = std::min<uint64_t>((uint64_t)n, pos + sz);
         const uint64_t kmax = std::min<uint64_t>(p1 - pos, (uint64_t)active);
         phase_begin(c, 2, ph);
-        fill_u32(c, &sh->k, 1, 0u);
-        hipLaunchKernelGGL(k_select_sources, dim3(grid_for(c, p1 - pos)), dim3(kBlock), 0, c->stream, P, (uint32_t)pos,
-                           (uint32_t)p1, c->label.p, c->srcvert.p, c->srclab.p, sh);
-        LAUNCHCHK("k_select_sources");
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kBlock), 0, c->stream, sh, &c->dctl->lane[0], &c->dctl->lane[1]);
+        LAUNCHCHK("k_batch_reset");
+        if ((p1 - pos) * 16 > (uint64_t)n) {
+            hipLaunchKernelGGL(k_select_scan, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, P,
+                               (uint32_t)pos, (uint32_t)p1, n, c->label.p, c->srcvert.p, c->srclab.p, sh);
+            LAUNCHCHK("k_select_scan");
+        } else {
+            hipLaunchKernelGGL(k_select_sources, dim3(grid_for(c, p1 - pos)), dim3(kBlock), 0, c->stream, P,
+                               (uint32_t)pos, (uint32_t)p1, c->label.p, c->srcvert.p, c->srclab.p, sh);
+            LAUNCHCHK("k_select_sources");
+        }
         pos = p1;
         // Section 4.5: next table size = nextpow2(max(0.3 b, 1.5 a)), b = |V'|,
         // a = pairs found by the previous search in the same direction.
@@ -951,8 +1020,9 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         for (int d = 0; d < 2; d++)
             ensure_lane(c, d, std::max<uint64_t>(d ? ts_in : ts_out, (uint64_t)n), c->bag_lam_log2);
         resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_rs).count();
+        SeedArgs SA;
+        memset(&SA, 0, sizeof SA);
         for (int d = 0; d < 2; d++) {
-            reset_lane_ctl(c, d);
             DevBuf<uint64_t> &T = d ? c->Tin : c->Tout;
             uint64_t &ts = d ? ts_in : ts_out;
             L[d] = Lane();
@@ -968,10 +1038,15 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             L[d].S.srclab = c->srclab.p;
             L[d].S.table = T.p;
             L[d].S.tmask = ts - 1;
-            hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, kmax)), dim3(kBlock), 0, c->stream, c->srcvert.p, sh, T.p,
-                               ts - 1, kProbeLimit, c->F[d].p, &c->dctl->lane[d], &c->dctl->ls[d]);
-            LAUNCHCHK("k_seed_multi");
+            SA.T[d] = T.p;
+            SA.mask[d] = ts - 1;
+            SA.F[d] = c->F[d].p;
+            SA.rc[d] = &c->dctl->lane[d];
+            SA.ls[d] = &c->dctl->ls[d];
         }
+        hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, kmax), 2), dim3(kBlock), 0, c->stream, c->srcvert.p, sh, SA,
+                           kProbeLimit);
+        LAUNCHCHK("k_seed_multi");
         DP.nsub = active;
         c->epoch = epoch;
         drive(c, L, 2, DP);
@@ -1176,9 +1251,18 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
         HIPCHK(hipGetDeviceProperties(&prop, device));
         c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         int nb = 0;
-        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand<kMulti>, kBlock, 0));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand<kMulti, 1>, kBlock, 0));
         if (nb < 1) nb = 1;
         c->expand_blocks = c->num_cu * nb;
+        // one resident wave of blocks per expand variant: its waves take the
+        // frontier's groups statically, so blocks beyond the resident set
+        // would run a second, serial local search
+        for (int m = 0; m < 2; m++)
+            for (int ai = 0; ai < 3; ai++) {
+                int b = 0;
+                HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, expand_kernel(m, 1 << ai), kBlock, 0));
+                c->expand_grid[m][ai] = c->num_cu * std::max(b, 1);
+            }
         if (stream) {
             c->stream = (hipStream_t)stream;
         } else {
@@ -1293,7 +1377,7 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
             HIPCHK(hipStreamSynchronize(c->stream));
             HIPCHK(hipMemcpyAsync(&lab, labels + s, 4, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            ensure_lane(c, 0, (uint64_t)n, (uint32_t)o.lambda_log2);
+            ensure_lane(c, 0, (uint64_t)n, lam_log2_for(o, (uint64_t)n));
             reset_bag(c, 0);
             Perm P0{(uint32_t)n, 1, 0};
             hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, labels, lab, s,
@@ -1321,10 +1405,17 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
             ensure(c, c->Tout, ts, &grew);
             fill_u64(c, c->Tout.p, grew ? c->Tout.cap : ts, kEmpty64);
             c->tables_dirty = true;
-            ensure_lane(c, 0, std::max<uint64_t>(ts, (uint64_t)n), (uint32_t)o.lambda_log2);
+            ensure_lane(c, 0, std::max<uint64_t>(ts, (uint64_t)n), lam_log2_for(o, std::max<uint64_t>(ts, (uint64_t)n)));
             reset_bag(c, 0);
-            hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)k)), dim3(kBlock), 0, c->stream, c->srcvert.p, sh,
-                               c->Tout.p, ts - 1, kProbeLimit, c->F[0].p, &c->dctl->lane[0], &c->dctl->ls[0]);
+            SeedArgs SA;
+            memset(&SA, 0, sizeof SA);
+            SA.T[0] = c->Tout.p;
+            SA.mask[0] = ts - 1;
+            SA.F[0] = c->F[0].p;
+            SA.rc[0] = &c->dctl->lane[0];
+            SA.ls[0] = &c->dctl->ls[0];
+            hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, (uint64_t)k), 1), dim3(kBlock), 0, c->stream, c->srcvert.p,
+                               sh, SA, kProbeLimit);
             LAUNCHCHK("k_seed_multi");
             L.mode = kMulti;
             L.T = &c->Tout;
@@ -1486,7 +1577,7 @@ scc_status scc_bag_selftest(scc_ctx_t *c, const uint64_t *keys, int64_t n, int32
         check_opts(c, o);
         init_call(c, stats, n, 0, &o);
         const uint64_t per_round = (uint64_t)((n + rounds - 1) / rounds);
-        ensure_lane(c, 0, std::max<uint64_t>(per_round, 1), (uint32_t)o.lambda_log2);
+        ensure_lane(c, 0, std::max<uint64_t>(per_round, 1), lam_log2_for(o, std::max<uint64_t>(per_round, 1)));
         ensure(c, c->F[0], (uint64_t)n + kWave);
         reset_bag(c, 0);
         Search S = make_search(c, 0, o, kSingle);
