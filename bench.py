@@ -30,7 +30,10 @@ WORKLOADS = {
     "knn_10M_k5": (2, "directed 5-NN graph of 1e7 points, mixture of 1000 isotropic Gaussians (sigma .01) "
                       "in the unit cube, ties to the lower id"),
     "grid10000_p0.5": (3, "2-D grid 10000x10000 (no wrap), each neighbour arc kept with p=0.5"),
+    "batched4096": (4, "4096 graphs, vertex counts log-uniform in [1e3, 1e5], family uniform in {torus p=0.5, "
+                       "R-MAT edge factor 8, 3-D k-NN k=5}, run as one disjoint union with an autotuned schedule"),
 }
+BATCH_G, BATCH_LO, BATCH_HI, BATCH_SEED = 4096, 3.0, 5.0, 1004
 # the frontier kernels timed with options.timing, as rocprofv3 names them
 KERNEL_NAMES = ["hipscc::k_expand<0, 1>", "hipscc::k_expand<1, 1>", "hipscc::k_pull", "hipscc::k_expand_heavy<0>",
                 "hipscc::k_expand_heavy<1>", "hipscc::k_bag_extract"]
@@ -74,6 +77,104 @@ def cpu_baseline(g, runs):
                  "sample": "whole graph, %d run(s) of the sequential Tarjan oracle, mean %.3f s" % (runs, t)}
 
 
+def run_batched(args, desc):
+    """The batched workload: many graphs resident in HBM, one scc_labels_batched
+    call per step with the schedule the autotuner picked; the same batch run
+    with the default schedule and as a loop of per-graph scc_labels calls is
+    timed once for comparison (outside the timed region)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import oracle
+    import paper_2303_04934_amd as scc
+    from paper_2303_04934_amd import autotune
+
+    t0 = time.perf_counter()
+    graphs = graphgen.batched(BATCH_G, BATCH_SEED, BATCH_LO, BATCH_HI)
+    vb, ab, oo, oa, io, ia = graphgen.concat(graphs)
+    print("[bench] generated %d graphs, n=%d m=%d in %.1f s" % (len(graphs), vb[-1], ab[-1], time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).to("cuda:0")
+    arrs = (dev(oo), dev(oa), dev(io), dev(ia))
+    base = scc.default_options(validate=0)
+    t0 = time.perf_counter()
+    opts, tuned = autotune.tune(vb, ab, *arrs, base_options=base)
+    print("[bench] autotune picked tau=%d beta=%.1f in %.1f s" % (opts.tau, opts.beta, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    # warm-up; its last call times every frontier kernel to pick the dominant one
+    for i in range(max(args.warmup, 1)):
+        opts.timing = (1 << NK) - 1 if i == max(args.warmup, 1) - 1 else 0
+        _, st = scc.scc_labels_batched(vb, ab, *arrs, options=opts, return_stats=True)
+    dom = max(range(NK), key=lambda i: st["ms_kernel"][i])
+    probe_ms = list(st["ms_kernel"])
+    opts.timing = 1 << dom
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, st = scc.scc_labels_batched(vb, ab, *arrs, options=opts, return_stats=True)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    got = out.cpu().numpy()
+    print("[bench] timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3), file=sys.stderr, flush=True)
+    # comparisons (untimed region): default schedule, and one scc_labels call per graph
+    base.timing = opts.timing  # the same event overhead as the timed steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scc.scc_labels_batched(vb, ab, *arrs, options=base)
+    base.timing = 0
+    torch.cuda.synchronize()
+    default_ms = (time.perf_counter() - t0) * 1e3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop_out = []
+    for g in range(len(graphs)):
+        n, lo = int(vb[g + 1] - vb[g]), int(vb[g]) + g
+        dg = scc.DeviceGraph(n, int(ab[g + 1] - ab[g]), arrs[0][lo:lo + n + 1], arrs[1][int(ab[g]):int(ab[g + 1])],
+                             arrs[2][lo:lo + n + 1], arrs[3][int(ab[g]):int(ab[g + 1])])
+        loop_out.append(scc.scc_labels(dg, base))
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3
+    loop_same = all(np.array_equal(loop_out[g].cpu().numpy(), got[vb[g]:vb[g + 1]]) for g in range(len(graphs)))
+    print("[bench] default schedule %.1f ms, per-graph loop %.1f ms" % (default_ms, loop_ms), file=sys.stderr,
+          flush=True)
+    m = int(ab[-1])
+    line = {
+        "metric": METRIC, "value": m / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batched4096", "description": desc, "graphs": len(graphs), "n": int(vb[-1]), "m": m,
+                   "seed": BATCH_SEED, "tau": opts.tau, "beta": opts.beta, "schedule": "autotuned"},
+        "batched_vs_plain": {"autotuned_batched_ms": dt * 1e3, "default_batched_ms": default_ms,
+                             "per_graph_loop_ms": loop_ms, "loop_labels_identical": loop_same,
+                             "autotune": tuned},
+    }
+    per_launch_ms = sum(s["ms_kernel"][dom] for s in stats) / max(1, sum(s["launches_kernel"][dom] for s in stats))
+    per_launch_bytes = sum(s["bytes_kernel"][dom] for s in stats) / max(1, sum(s["launches_kernel"][dom] for s in stats))
+    if per_launch_ms > 0:
+        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        line["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                            "avg_launch_ms": per_launch_ms, "alg_bytes_per_launch": per_launch_bytes}
+    line["stats"] = {"kernel_ms_warmup_call": {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)},
+                     "batches": stats[-1]["batches"], "rounds_first": stats[-1]["rounds_first"],
+                     "rounds_multi": stats[-1]["rounds_multi"]}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        ok = True
+        for g, gr in enumerate(graphs):
+            ok = ok and bool(np.array_equal(oracle.scc_graph(gr), got[vb[g]:vb[g + 1]]))
+        t = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                                "sample": "every graph of the batch, sequential Tarjan oracle, %.1f s" % t}
+        line["parity"] = "bit-exact vs oracle" if ok else "MISMATCH vs oracle"
+    print(json.dumps(line), flush=True)
+    if line.get("parity", "").startswith("MISMATCH"):
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,13 +203,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    cfg, desc = WORKLOADS[args.workload]
+    if args.workload == "batched4096":
+        run_batched(args, desc)
+        return
+
     import numpy as np
     import torch
 
     import graphgen
     import paper_2303_04934_amd as scc
 
-    cfg, desc = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     g = graphgen.config(cfg, shrink=args.shrink)
     print("[bench] generated %s n=%d m=%d in %.1f s" % (args.workload, g.n, g.m, time.perf_counter() - t0),

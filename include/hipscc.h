@@ -69,7 +69,9 @@ typedef struct {
  *                tau <= 1 disables local search (plain frontier BFS,
  *                Algorithm 2).
  *   beta         prefix-doubling multiplier for the source batches
- *                (Algorithm 1; Table 1 uses 1.5).  Must be > 1.
+ *                (Algorithm 1 doubles; Table 1 uses 1.5; any constant > 1
+ *                keeps the bounds).  Default 2: fewer, larger batches mean
+ *                fewer latency-bound rounds on the GPU.  Must be > 1.
  *   lambda_log2  log2 of the hash bag's first chunk (Table 1: 10 for tens of
  *                threads).  0 (default) = automatic: up to 2^20 slots, so that
  *                thousands of inserting wavefronts spread over many stripes.

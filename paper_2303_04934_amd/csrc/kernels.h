@@ -3,6 +3,7 @@
 
 #include "bag.h"
 #include "device.h"
+#include "policy.h"
 
 namespace hipscc {
 
@@ -138,6 +139,9 @@ struct Search {
     uint32_t vgc_cut;       // local search only while the frontier has fewer entries than this ...
     unsigned long long vgc_arcs;  // ... or, when its degree sum is known, fewer arcs than this
     uint32_t tau_from_rc;   // 1: the budget of each round is rc->tau_cur (set by the policy)
+    const float *policy_w;  // non-null: ExtractAll's last block runs the policy for the next round
+    float nsub;             // subproblem size (policy feature)
+    uint32_t fallback_tau;  // budget when the policy's scores are unusable
 };
 
 // ------------------------------------------------------------- utilities ----
@@ -1079,9 +1083,30 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(LanePair P) {
         last = atomicAdd(&S.bag.ctl->done_blocks, 1u) == nblk - 1;
     }
     __syncthreads();
-    if (last && threadIdx.x == 0) {
+    if (!last) return;  // block-uniform
+    if (threadIdx.x == 0) {
         __threadfence();
         extract_reset(S, S.par);
+    }
+    if (S.policy_w) {
+        // the learned policy picks the next round's budget here, where the new
+        // frontier's statistics are complete, instead of in a launch of its own
+        __shared__ float x[kPolicyIn], h1[kPolicyHidden], h2[kPolicyHidden], y[kPolicyOut];
+        __shared__ uint32_t nf;
+        RoundCtl *rc = S.rc;
+        const int np = S.par ^ 1;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            nf = rc->nF[np];
+            policy_features((float)nf, (float)rc->fdeg[np], (float)rc->claims, S.nsub, (float)rc->rounds,
+                            (float)rc->lsdepth[S.par], x);
+        }
+        __syncthreads();
+        if (nf == 0) return;  // block-uniform: no next round
+        if (threadIdx.x < kWave) policy_forward_wave(S.policy_w, x, y, h1, h2);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            policy_pick(y, 1u, S.fallback_tau, &rc->tau_cur, &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks);
     }
 }
 

@@ -16,9 +16,9 @@ constexpr int kPolicyHidden = 32;
 constexpr int kPolicyOut = 8;
 constexpr int kPolicyFloats = kPolicyHidden * kPolicyIn + kPolicyHidden + kPolicyHidden * kPolicyHidden +
                               kPolicyHidden + kPolicyOut * kPolicyHidden + kPolicyOut;
-// VGC budgets of the four classes (64, 256, 1024, 4096); class c with mode m
-// is output 2 c + m.
-__host__ __device__ __forceinline__ uint32_t policy_tau(int c) { return 64u << (2 * c); }
+// VGC budgets of the four classes (512, 1024, 2048, 4096 arcs per wavefront
+// task); class c with mode m is output 2 c + m.
+__host__ __device__ __forceinline__ uint32_t policy_tau(int c) { return 512u << c; }
 
 struct Policy {
     float *w = nullptr;    // device weights
@@ -125,21 +125,31 @@ __device__ __forceinline__ void policy_pick(const float *y, uint32_t mode_mask, 
     }
 }
 
-// The policy step before a round, as its own launch (one wave).
-__global__ __launch_bounds__(64) void k_policy_round(const float *W, const uint32_t *nF2, const unsigned long long *fdeg,
-                                                     const unsigned long long *claims, const uint32_t *rounds,
-                                                     const uint32_t *lsdepth, float nsub, uint32_t mode_mask,
-                                                     uint32_t fallback_tau, uint32_t *tau_cur, uint32_t *mode_pref,
-                                                     uint32_t *calls, uint32_t *fallbacks) {
+// Where one search lane keeps the policy's inputs and outputs.
+struct PolicyLane {
+    const uint32_t *nF2;               // frontier sizes of both parities
+    const unsigned long long *fdeg;    // degree sum of the coming frontier
+    const unsigned long long *claims;
+    const uint32_t *rounds;
+    const uint32_t *lsdepth;           // deepest local search of the previous round
+    float nsub;                        // subproblem size
+    uint32_t *tau_cur, *mode_pref, *calls, *fallbacks;
+};
+
+// The policy step before a round, one launch for up to two lanes (block b =
+// lane b, one wave each).
+__global__ __launch_bounds__(64) void k_policy_round(const float *W, PolicyLane L0, PolicyLane L1, uint32_t mode_mask,
+                                                     uint32_t fallback_tau) {
     __shared__ float x[kPolicyIn], h1[kPolicyHidden], h2[kPolicyHidden], y[kPolicyOut];
-    const uint32_t nf = nF2[0] + nF2[1];
+    const PolicyLane &L = blockIdx.x == 0 ? L0 : L1;
+    const uint32_t nf = L.nF2[0] + L.nF2[1];
     if (nf == 0) return;
     if (threadIdx.x == 0)
-        policy_features((float)nf, (float)*fdeg, (float)*claims, nsub, (float)*rounds, (float)*lsdepth, x);
+        policy_features((float)nf, (float)*L.fdeg, (float)*L.claims, L.nsub, (float)*L.rounds, (float)*L.lsdepth, x);
     __syncthreads();
     policy_forward_wave(W, x, y, h1, h2);
     __syncthreads();
-    if (threadIdx.x == 0) policy_pick(y, mode_mask, fallback_tau, tau_cur, mode_pref, calls, fallbacks);
+    if (threadIdx.x == 0) policy_pick(y, mode_mask, fallback_tau, L.tau_cur, L.mode_pref, L.calls, L.fallbacks);
 }
 
 inline void policy_release(Policy &p) {

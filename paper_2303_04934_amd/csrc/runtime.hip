@@ -22,7 +22,6 @@
 
 #include "hipscc.h"
 #include "kernels.h"
-#include "policy.h"
 
 using namespace hipscc;
 
@@ -239,7 +238,7 @@ scc_options_t defaults() {
     scc_options_t o;
     memset(&o, 0, sizeof o);
     o.tau = 2048;
-    o.beta = 1.5f;
+    o.beta = 2.0f;
     o.lambda_log2 = 0;
     o.sigma = 50;
     o.kappa = 8;
@@ -359,6 +358,7 @@ struct Lane {
     uint32_t tau_used = 0;
     int64_t nsub = 1;
     double avg_deg = 1.0;    // arcs per vertex of the graph (local-search cut)
+    bool policy_primed = false;  // the learned policy has picked this search's first budget
     // single source
     bool dense = false, have_list = true;
     const int32_t *roff = nullptr, *radj = nullptr;
@@ -381,25 +381,42 @@ struct DriveParams {
 // last-block ticket costs one atomic per block, so a modest grid suffices.
 unsigned extract_blocks(scc_ctx *c) { return (unsigned)std::max(c->num_cu / 2, 1); }
 
-// Before a round: the learned policy picks the round's budget (and preferred
-// mode) on the device; exploration draws a random budget class.
-void launch_policy(scc_ctx *c, Lane &L, const scc_options_t &o, int dense_opt) {
-    Search &S = L.S;
+// Before a round: the learned policy picks each sparse lane's budget on the
+// device (one launch for the round's lanes); exploration draws a random
+// budget class per lane.  The frontier mode stays with the direction rule
+// (dense rounds were too rare in the training traces to rank them).
+void launch_policy(scc_ctx *c, Lane **ls, int nl, const scc_options_t &o) {
+    if (nl == 0) return;
     if (o.policy == 1 && c->policy.loaded) {
-        RoundCtl *rc = S.rc;
-        // the policy picks the budget among sparse actions; the frontier mode
-        // stays with the direction rule (dense rounds were too rare in the
-        // training traces to rank them reliably)
-        const uint32_t mask = 1u;
-        hipLaunchKernelGGL(k_policy_round, dim3(1), dim3(64), 0, c->stream, c->policy.w, rc->nF, &rc->fdeg[L.par], &rc->claims,
-                           &rc->rounds, &rc->lsdepth[L.par ^ 1], (float)L.nsub, mask, (uint32_t)std::max(o.tau, 0), &rc->tau_cur,
-                           &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks);
-        LAUNCHCHK("k_policy_round");
-        S.tau_from_rc = 1;
+        // a search's first round gets its budget from a launch of its own;
+        // later rounds get it from the previous round's ExtractAll (traced
+        // runs keep the launch, so that a row records the budget it used)
+        PolicyLane P[2];
+        memset(P, 0, sizeof P);
+        int np = 0;
+        for (int j = 0; j < nl; j++) {
+            Lane &L = *ls[j];
+            L.S.tau_from_rc = 1;
+            L.S.policy_w = c->tracing ? nullptr : c->policy.w;
+            L.S.nsub = (float)L.nsub;
+            L.S.fallback_tau = (uint32_t)std::max(o.tau, 0);
+            if (L.policy_primed && !c->tracing) continue;
+            RoundCtl *rc = L.S.rc;
+            P[np++] = PolicyLane{rc->nF, &rc->fdeg[L.par], &rc->claims, &rc->rounds, &rc->lsdepth[L.par ^ 1],
+                                 (float)L.nsub, &rc->tau_cur, &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks};
+            L.policy_primed = true;
+        }
+        if (np) {
+            hipLaunchKernelGGL(k_policy_round, dim3(np), dim3(64), 0, c->stream, c->policy.w, P[0], P[np > 1 ? 1 : 0],
+                               1u, (uint32_t)std::max(o.tau, 0));
+            LAUNCHCHK("k_policy_round");
+        }
     } else if (o.policy == 2) {
-        c->explore_state = mix64(c->explore_state + 0x9E3779B97F4A7C15ull);
-        S.tau = (int32_t)policy_tau((int)(c->explore_state >> 62));
-        S.tau_from_rc = 0;
+        for (int j = 0; j < nl; j++) {
+            c->explore_state = mix64(c->explore_state + 0x9E3779B97F4A7C15ull);
+            ls[j]->S.tau = (int32_t)policy_tau((int)(c->explore_state >> 62));
+            ls[j]->S.tau_from_rc = 0;
+        }
     }
 }
 
@@ -566,6 +583,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
         L.rounds = 0;
         L.nsub = std::max<int64_t>(P.nsub, 1);
         L.avg_deg = P.n > 0 ? std::max(1.0, (double)P.m / (double)P.n) : 1.0;
+        L.policy_primed = false;
     }
     const uint64_t arcs_on = (uint64_t)std::max<int64_t>(P.m / 14, 1);
     const int64_t back_off = std::max<int64_t>(P.nsub / 24, 1);
@@ -607,8 +625,11 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 if (c->tracing) {
                     hipLaunchKernelGGL(k_trace_snap, dim3(1), dim3(64), 0, c->stream, L.S.rc, L.par);
                     LAUNCHCHK("k_trace_snap");
+                    if (!L.dense) {
+                        Lane *one = &L;
+                        launch_policy(c, &one, 1, o);
+                    }
                 }
-                launch_policy(c, L, o, dense_opt);
                 if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][0], c->stream));
                 was_dense[L.id] = L.dense;
                 if (L.dense) {
@@ -622,6 +643,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 }
                 if (c->tracing) HIPCHK(hipEventRecord(c->rev[L.id][1], c->stream));
             }
+            launch_policy(c, sp, nsp, o);
             if (nsp == 2 && sp[0]->mode != sp[1]->mode) {
                 launch_sparse(c, &sp[0], 1);
                 launch_sparse(c, &sp[1], 1);
@@ -659,6 +681,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 restart_multi(c, L, P);
                 L.fdeg = L.claims = 0;
                 L.rounds = 0;
+                L.policy_primed = false;
                 continue;
             }
             L.fdeg = rc.fdeg[rc.nF[0] ? 0 : 1];
@@ -696,6 +719,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 LAUNCHCHK("k_bitmap_to_list");
                 L.dense = false;
                 L.have_list = true;
+                L.policy_primed = false;
                 switched = true;
             }
         }

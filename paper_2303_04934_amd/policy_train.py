@@ -4,20 +4,24 @@ The policy is a float32 MLP 5 -> 32 -> 32 -> 8 (ReLU) that the library runs
 on the device before every search round (``options.policy = 1``).  Its inputs
 are the round features of ``scc_trace_read`` (frontier size, frontier degree
 sum, visited fraction, round index, deepest local search of the previous
-round); output 2c + m scores budget class c (64 * 4^c arcs) with frontier mode
-m (0 sparse, 1 dense).  The library takes the best allowed output.
+round); output 2c + m scores budget class c (512 * 2^c arcs per wavefront
+task) with frontier mode m (0 sparse, 1 dense).  The library takes the best allowed output.
 
-Training data are per-round traces of runs that draw a random budget class
-every round (``options.policy = 2``) on training graphs whose seeds (>= 10^6)
-are disjoint from the benchmark inputs.  Each row gives the taken action and
-the round's outcome; the regression target is the round's progress rate
-log((entries claimed + 1) / (round ms + launch overhead)).  Only the taken
-action's output is trained (dense rounds train all four dense outputs, whose
-budget does not matter).  The policy only chooses schedules: the SCC labels
-do not depend on it.
+Training data come from graphs whose seeds (>= 10^6) are disjoint from the
+benchmark inputs.  For every training graph each budget class is run with a
+fixed budget, timed end to end, and traced (one feature row per round).
+Every traced row of a graph is labelled, for each class c, with the score
+-log(T(c) / min_c' T(c')), where T(c) is the graph's whole-run time with
+class c: the regret of that class on graphs whose rounds look like this one.
+The MLP regresses the four sparse-mode scores (the dense outputs are not
+trained: the frontier mode stays with the direction rule), so at run time
+it picks, round by round, the class that did best on rounds of that kind.
+An earlier target, the round's own progress rate, was dominated by state
+noise and picked budgets that lost on every benchmark graph.  The policy
+only chooses schedules: the SCC labels do not depend on it.
 
-    python -m paper_2303_04934_amd.policy_train collect --out traces.npy   # on a GPU
-    python -m paper_2303_04934_amd.policy_train fit traces.npy --out policy_weights.npy
+    python -m paper_2303_04934_amd.policy_train collect --out traces.npz   # on a GPU
+    python -m paper_2303_04934_amd.policy_train fit traces.npz --out policy_weights.npy
 """
 from __future__ import annotations
 
@@ -30,7 +34,6 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "policy_weights.npy")
 N_IN, HID, N_OUT = 5, 32, 8
-ROUND_OVERHEAD_MS = 0.03  # launch + check cost a round adds beyond its kernels
 
 
 def n_params():
@@ -57,32 +60,28 @@ def forward(w, x):
     return h2 @ W3.T + b3, (h1, h2)
 
 
-def dataset(rows):
-    """(features, action mask, target) from trace rows."""
+def dataset(rows, scores):
+    """(features, output mask, targets) from trace rows and per-row class scores."""
     rows = np.asarray(rows, np.float64)
     x = rows[:, 1:6].astype(np.float32)
-    kind, tau, ms, claims = rows[:, 0], rows[:, 6], rows[:, 7], rows[:, 8]
-    y = np.log((claims + 1.0) / (ms + ROUND_OVERHEAD_MS)).astype(np.float32)
+    y = np.zeros((len(rows), N_OUT), np.float32)
     mask = np.zeros((len(rows), N_OUT), np.float32)
-    cls = np.clip(np.round(np.log(np.maximum(tau, 64) / 64.0) / np.log(4.0)), 0, 3).astype(int)
-    dense = kind == 1
-    mask[~dense, 2 * cls[~dense]] = 1.0
-    mask[dense, 1::2] = 1.0
+    y[:, 0::2] = scores
+    mask[:, 0::2] = 1.0
     return x, mask, y
 
-
-def fit(rows, steps=4000, lr=3e-3, seed=0, verbose=True):
-    """Masked-MSE regression of the taken actions' rates; Adam, full batch."""
-    x, mask, y = dataset(rows)
+def fit(rows, scores, steps=4000, lr=3e-3, seed=0, verbose=True):
+    """Masked-MSE regression of the class scores; Adam, full batch."""
+    x, mask, y = dataset(rows, scores)
     rng = np.random.default_rng(seed)
     p = [rng.standard_normal((HID, N_IN)) * np.sqrt(2 / N_IN), np.zeros(HID),
          rng.standard_normal((HID, HID)) * np.sqrt(2 / HID), np.zeros(HID),
-         rng.standard_normal((N_OUT, HID)) * np.sqrt(1 / HID), np.full(N_OUT, float(y.mean()))]
+         rng.standard_normal((N_OUT, HID)) * np.sqrt(1 / HID), np.full(N_OUT, float(y[mask > 0].mean()))]
     p = [a.astype(np.float64) for a in p]
     m = [np.zeros_like(a) for a in p]
     v = [np.zeros_like(a) for a in p]
     X = x.astype(np.float64)
-    Y = y.astype(np.float64)[:, None]
+    Y = y.astype(np.float64)
     M = mask.astype(np.float64)
     cnt = max(M.sum(), 1.0)
     for it in range(1, steps + 1):
@@ -115,32 +114,59 @@ def fit(rows, steps=4000, lr=3e-3, seed=0, verbose=True):
 
 
 def training_graphs():
-    """Small graphs of every family with seeds disjoint from the benchmark inputs."""
+    """Graphs of every family with seeds disjoint from the benchmark inputs."""
     import graphgen
     out = []
-    for i in range(2):
+    for i in range(3):
         s = 1_000_000 + 17 * i
-        out.append(graphgen.torus(400 + 100 * i, 500, 0.5, seed=s))
-        out.append(graphgen.grid(800 + 200 * i, 800, 0.5, seed=s + 1))
-        out.append(graphgen.knn(400_000 + 200_000 * i, 40 + 20 * i, 5, 0.01, seed=s + 2))
+        out.append(graphgen.torus(500 + 200 * i, 500 + 200 * i, 0.5, seed=s))
+        out.append(graphgen.grid(1000 + 500 * i, 1000 + 250 * i, 0.5, seed=s + 1))
+        out.append(graphgen.knn(500_000 + 1_000_000 * i, 50 + 100 * i, 5, 0.01, seed=s + 2))
         out.append(graphgen.rmat(17 + i, 16, seed=s + 3))
     return out
 
 
-def collect(runs_per_graph=3, verbose=True):
-    """Exploration traces (random budget class per round) on the training graphs."""
+def collect(repeats=4, verbose=True):
+    """For every training graph and budget class: the whole-run time with that
+    fixed budget (best of `repeats`) and one traced run's rows."""
+    import time
+
+    import torch
+
     import paper_2303_04934_amd as scc
-    rows = []
+    rows, gids, times = [], [], []
     for gi, g in enumerate(training_graphs()):
         dg = scc.to_device(g)
-        for r in range(runs_per_graph):
-            o = scc.default_options(policy=2, trace=1, seed=1_000_003 + 31 * gi + r, validate=0)
-            scc.scc_labels(dg, o)
+        out = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
+        t_g = []
+        for c in range(4):
+            tau = 512 << c
+            o = scc.default_options(tau=tau, validate=0, seed=1_000_003 + gi)
+            scc.scc_labels(dg, o, out=out)
+            ts = []
+            for _ in range(repeats):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                scc.scc_labels(dg, o, out=out)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t_g.append(min(ts))
+            o.trace = 1
+            scc.scc_labels(dg, o, out=out)
             t = scc.trace_read()
             rows.append(t)
-            if verbose:
-                print("[collect] %s run %d: %d rows" % (g.name, r, len(t)), flush=True)
-    return np.concatenate(rows) if rows else np.zeros((0, 12), np.float32)
+            gids.append(np.full(len(t), gi, np.int32))
+        times.append(t_g)
+        if verbose:
+            print("[collect] %s: class times ms %s" % (g.name, ["%.2f" % (1e3 * v) for v in t_g]), flush=True)
+    return np.concatenate(rows), np.concatenate(gids), np.asarray(times)
+
+
+def scores_for(gids, times):
+    """Per-row class scores -log(T(c) / min T) of the row's graph."""
+    t = np.asarray(times, np.float64)
+    sc = -np.log(t / t.min(axis=1, keepdims=True))
+    return sc[np.asarray(gids)].astype(np.float32)
 
 
 def main(argv=None):
@@ -148,19 +174,23 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
     c.add_argument("--out", required=True)
-    c.add_argument("--runs", type=int, default=3)
+    c.add_argument("--repeats", type=int, default=4)
     f = sub.add_parser("fit")
     f.add_argument("traces", nargs="+")
     f.add_argument("--out", default=WEIGHTS)
     f.add_argument("--steps", type=int, default=4000)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
-        rows = collect(a.runs)
-        np.save(a.out, rows)
-        print("saved %d rows to %s" % (len(rows), a.out))
+        rows, gids, times = collect(a.repeats)
+        np.savez(a.out, rows=rows, gids=gids, times=times)
+        print("saved %d rows of %d graphs to %s" % (len(rows), len(times), a.out))
     else:
-        rows = np.concatenate([np.load(p) for p in a.traces])
-        w = fit(rows, steps=a.steps)
+        xs, ss = [], []
+        for p in a.traces:
+            d = np.load(p)
+            xs.append(d["rows"])
+            ss.append(scores_for(d["gids"], d["times"]))
+        w = fit(np.concatenate(xs), np.concatenate(ss), steps=a.steps)
         assert w.size == n_params()
         np.save(a.out, w)
         print("saved %d weights to %s" % (w.size, a.out))

@@ -1,0 +1,31 @@
+"""Batched execution (many graphs as one disjoint union) against the oracle,
+with the schedule autotuner's choice, and the per-graph loop it replaces."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotuned_batch_matches_oracle_and_per_graph_calls(gpu):
+    import torch
+    from paper_2303_04934_amd import autotune
+    graphs = graphgen.batched(300, seed=4242, lo_exp=2.0, hi_exp=4.0)
+    vb, ab, oo, oa, io, ia = graphgen.concat(graphs)
+    print("[case] autotuned batch", len(graphs), "graphs", int(vb[-1]), "vertices", int(ab[-1]), "arcs", flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+    arrs = (t(oo), t(oa), t(io), t(ia))
+    opts, rep = autotune.tune(vb, ab, *arrs, sample_arcs=200_000, repeats=1)
+    assert (opts.tau, opts.beta) in [(c[0], pytest.approx(c[1])) for c in autotune.CANDIDATES]
+    assert len(rep["candidates"]) == len(autotune.CANDIDATES) and rep["sample_graphs"] > 0
+    got = gpu.scc_labels_batched(vb, ab, *arrs, options=opts).cpu().numpy()
+    for g, gr in enumerate(graphs):
+        assert np.array_equal(got[vb[g]:vb[g + 1]], oracle.scc_graph(gr)), "graph %d" % g
+    # the same graphs one call each (device views of the batch arrays)
+    for g in range(0, len(graphs), 37):
+        n, lo = int(vb[g + 1] - vb[g]), int(vb[g]) + g
+        dg = gpu.DeviceGraph(n, int(ab[g + 1] - ab[g]), arrs[0][lo:lo + n + 1], arrs[1][int(ab[g]):int(ab[g + 1])],
+                             arrs[2][lo:lo + n + 1], arrs[3][int(ab[g]):int(ab[g + 1])])
+        assert np.array_equal(gpu.scc_labels(dg).cpu().numpy(), got[vb[g]:vb[g + 1]])

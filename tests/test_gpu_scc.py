@@ -80,7 +80,7 @@ def test_config0_full_size(gpu):
 @pytest.mark.parametrize("opt", [
     dict(tau=0), dict(tau=1), dict(tau=4), dict(tau=512, lambda_log2=10), dict(tau=65536),
     dict(seeds_per_wave=1), dict(seeds_per_wave=64),
-    dict(beta=1.1), dict(beta=2.0), dict(arcs_per_lane=1), dict(arcs_per_lane=2),
+    dict(beta=1.1), dict(beta=1.5), dict(beta=8.0), dict(arcs_per_lane=1), dict(arcs_per_lane=2),
     dict(arcs_per_lane=1, tau=512, lambda_log2=10),
     dict(lambda_log2=6, sigma=1, kappa=0),
     dict(table_init=1024), dict(trim=0), dict(seed=12345),
@@ -242,5 +242,5 @@ def test_policy_and_exploration_do_not_change_labels(gpu):
     st = check_labels(gpu, g, gpu.default_options(policy=2, trace=1), name="knn50k explore+trace")
     rows = gpu.trace_read()
     assert rows.shape[1] == gpu.TRACE_FIELDS and len(rows) == st["rounds_first"] + st["rounds_multi"]
-    assert set(np.unique(rows[:, 6])) <= {64.0, 256.0, 1024.0, 4096.0}
+    assert set(np.unique(rows[:, 6])) <= {512.0, 1024.0, 2048.0, 4096.0}
     check_labels(gpu, graphgen.rmat(13, 16, seed=22), gpu.default_options(policy=1, dense=-1), name="rmat13 learned")
