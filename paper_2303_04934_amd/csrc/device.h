@@ -32,20 +32,31 @@ __device__ __forceinline__ int rank_below(uint64_t mask) {
 
 __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
 
-// Wave-wide inclusive prefix sum (Hillis-Steele over 64 lanes).
+// Wave-wide inclusive prefix sum over 64 lanes with DPP lane moves (no LDS
+// round trips): Hillis-Steele within each row of 16 lanes (row_shr 1, 2, 4,
+// 8; lanes shifted in from outside the row read 0), then row 15's total is
+// added to rows 1 and 3 (row_bcast:15) and lane 31's to rows 2 and 3
+// (row_bcast:31).
 __device__ __forceinline__ int wave_incl_scan(int x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        int y = __shfl_up(x, d, kWave);
-        if (l >= d) x += y;
-    }
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowBcast15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowBcast31, 0xc, 0xf, false);
     return x;
 }
 
-__device__ __forceinline__ int wave_bcast(int x, int src) { return __shfl(x, src, kWave); }
+// Wave-wide sum of 32-bit values (the scan's last lane), in every lane.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readlane(wave_incl_scan((int)x), kWave - 1);
+}
+
+// Value of lane `src` (the same for every lane of the wave) in every lane.
+__device__ __forceinline__ int wave_bcast(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
 __device__ __forceinline__ uint32_t wave_bcast_u(uint32_t x, int src) {
-    return (uint32_t)__shfl((int)x, src, kWave);
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, src);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {

@@ -158,8 +158,7 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
 // of the block must call it.
 __device__ __forceinline__ void block_add_u32(uint32_t *ctr, uint32_t x) {
     __shared__ uint32_t part[kWavesPerBlock];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d, kWave);
+    x = wave_sum_u32(x);
     if (lane_id() == 0) part[threadIdx.x / kWave] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -194,8 +193,9 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t *ctr, uint32_t cnt) {
 // thread i < kNumCtr, the block's total of counter i.
 __device__ __forceinline__ unsigned long long block_flush_ctr(unsigned long long *dst, unsigned long long (&c)[kNumCtr]) {
     __shared__ unsigned long long part[kWavesPerBlock][kNumCtr];
+    // a lane's own counts stay far below 2^32 within one launch
 #pragma unroll
-    for (int i = 0; i < kNumCtr; i++) c[i] = wave_sum_u64(c[i]);
+    for (int i = 0; i < kNumCtr; i++) c[i] = wave_sum_u32((uint32_t)c[i]);
     if (lane_id() == 0)
         for (int i = 0; i < kNumCtr; i++) part[threadIdx.x / kWave][i] = c[i];
     __syncthreads();
