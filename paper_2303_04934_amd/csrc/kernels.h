@@ -872,12 +872,20 @@ __global__ __launch_bounds__(kBlock) void k_pull(int32_t n, const int32_t *off, 
         if (v < n && !((word >> (v & 31)) & 1u)) {
             c_exp++;
             const int32_t e1 = off[v + 1];
-            for (int32_t e = off[v]; e < e1; e++) {
-                const int32_t u = adj[e];
-                c_arcs++;
-                if ((front[u >> 5] >> (u & 31)) & 1u) {
-                    found = true;
-                    break;
+            // four predecessors per iteration: their ids, then their frontier
+            // words, are loaded together (one chain of two accesses per four arcs)
+            for (int32_t e = off[v]; e < e1 && !found; e += 4) {
+                int32_t u[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) u[i] = e + i < e1 ? adj[e + i] : -1;
+                uint32_t f[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) f[i] = u[i] >= 0 ? front[u[i] >> 5] : 0u;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    if (u[i] < 0 || found) continue;
+                    c_arcs++;
+                    found = (f[i] >> (u[i] & 31)) & 1u;
                 }
             }
         }
