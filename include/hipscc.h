@@ -101,6 +101,12 @@ typedef struct {
  *                a local-search step: 1, 2 or 4 (0 = default 1).  More arcs
  *                per lane shorten the chain of dependent memory accesses of a
  *                step but cost registers, hence resident wavefronts.
+ *   beta_fast    batches grow by beta_fast instead of beta after a cheap
+ *                batch: its sources reached fewer than 4 vertices each (per
+ *                direction) and its frontiers never exceeded the expand
+ *                grid's lanes, so a larger batch costs little.  Any growth
+ *                factor above 1 keeps Algorithm 1 correct.  Default 8;
+ *                <= beta turns it off.
  *   vgc_fill     local search runs in rounds whose frontier has fewer arcs
  *                (entries x average degree) than vgc_fill x the lanes of the
  *                expand grid; a frontier above that keeps the GPU busy on its
@@ -124,7 +130,8 @@ typedef struct {
     int32_t trace;
     int32_t arcs_per_lane;
     float vgc_fill;
-    int32_t reserved[3];
+    float beta_fast;
+    int32_t reserved[2];
 } scc_options_t;
 
 /* Frontier kernels timed with options.timing. */

@@ -31,7 +31,8 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("policy", ctypes.c_int32), ("dense", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("trim", ctypes.c_int32), ("table_init", ctypes.c_int64),
                 ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("trace", ctypes.c_int32),
-                ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+                ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float),
+                ("beta_fast", ctypes.c_float), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):

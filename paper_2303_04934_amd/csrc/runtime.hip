@@ -53,6 +53,7 @@ constexpr int kMaxSlots = 64;   // rounds per launch block
 constexpr int kTimedMax = 4 * kMaxSlots;  // timed launches between host checks
 constexpr int kPhases = 5;      // trim, first, multi, resize, label
 constexpr uint32_t kProbeLimit = 128;
+constexpr uint64_t kCheapPairs = 4;  // reach pairs per source of a batch that counts as cheap
 
 }  // namespace
 
@@ -239,6 +240,7 @@ scc_options_t defaults() {
     memset(&o, 0, sizeof o);
     o.tau = 2048;
     o.beta = 2.0f;
+    o.beta_fast = 8.0f;
     o.lambda_log2 = 0;
     o.sigma = 50;
     o.kappa = 8;
@@ -375,6 +377,7 @@ struct DriveParams {
     int64_t nsub = 0;        // active vertices (upper bound)
     scc_stats_t *st = nullptr;
     double *resize_ms = nullptr;
+    uint64_t peak_fdeg = 0;  // out: largest frontier degree sum seen at a host check
 };
 
 // ExtractAll grid: each block walks 256 stripes (16K slots) per step, and the
@@ -567,7 +570,7 @@ void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
 // rounds go in blocks of K (doubling up to 64) between checks.  Each round
 // expands entries claimed in the previous round, so a search has at most
 // (claimable entries + 1) rounds; the launch count guards the loop.
-void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
+void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
     const scc_options_t &o = *P.o;
     const int dense_opt = o.dense;
     const bool use_policy = o.policy == 1 && c->policy.loaded;
@@ -685,6 +688,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, const DriveParams &P) {
                 continue;
             }
             L.fdeg = rc.fdeg[rc.nF[0] ? 0 : 1];
+            P.peak_fdeg = std::max<uint64_t>(P.peak_fdeg, L.fdeg);
             L.claims = rc.claims;
             if (L.nf > 0 && nf_new > 0)
                 L.growth = std::pow((double)nf_new / (double)L.nf, 1.0 / (double)(L.dense ? 1 : k));
@@ -1002,11 +1006,16 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     // check); it is only used as an upper bound.
     uint64_t pos = j1 < (uint32_t)n ? (uint64_t)j1 + 1 : (uint64_t)n;
     double bsize = 1.0;
+    bool fast_next = false;
+    const uint64_t lanes_all = (uint64_t)c->expand_grid[kMulti][0] * kBlock;
     int32_t epoch = 1;
     uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0;
     int64_t active = (int64_t)n - trimmed;  // upper bound
     while (active > 0 && pos < (uint64_t)n) {
-        bsize *= (double)o.beta;
+        // Batches grow by beta (Algorithm 1), or by beta_fast after a batch
+        // whose frontiers never filled the GPU's lanes: its rounds were
+        // latency bound, so a larger batch costs few extra rounds' time.
+        bsize *= (o.beta_fast > o.beta && fast_next) ? (double)o.beta_fast : (double)o.beta;
         const uint64_t sz = std::max<uint64_t>((uint64_t)std::ceil(bsize - 1e-9), 1);
         const uint64_t p1 = std::min<uint64_t>((uint64_t)n, pos + sz);
         const uint64_t kmax = std::min<uint64_t>(p1 - pos, (uint64_t)active);
@@ -1072,12 +1081,16 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
                            kProbeLimit);
         LAUNCHCHK("k_seed_multi");
         DP.nsub = active;
+        DP.peak_fdeg = 0;
         c->epoch = epoch;
         drive(c, L, 2, DP);
         phase_end(c, ph);
         const uint32_t k = c->hctl->sh.k;
         a_out = c->hctl->lane[0].claims + k;
         a_in = c->hctl->lane[1].claims + k;
+        // a cheap batch: its sources reached few vertices each and its
+        // frontiers never filled the GPU, so the next one may grow faster
+        fast_next = DP.peak_fdeg < lanes_all && k > 0 && (a_out + a_in) < (uint64_t)kCheapPairs * 2 * k;
         active = (int64_t)n - trimmed - count_sum(c, &CountLine::fin);
         if (k == 0) continue;  // nothing was claimed; the tables are still clean
         if (st) {

@@ -80,7 +80,7 @@ def test_config0_full_size(gpu):
 @pytest.mark.parametrize("opt", [
     dict(tau=0), dict(tau=1), dict(tau=4), dict(tau=512, lambda_log2=10), dict(tau=65536),
     dict(seeds_per_wave=1), dict(seeds_per_wave=64),
-    dict(beta=1.1), dict(beta=1.5), dict(beta=8.0), dict(arcs_per_lane=1), dict(arcs_per_lane=2),
+    dict(beta=1.1), dict(beta=1.5), dict(beta=8.0), dict(beta_fast=0.0), dict(beta_fast=64.0), dict(arcs_per_lane=1), dict(arcs_per_lane=2),
     dict(arcs_per_lane=1, tau=512, lambda_log2=10),
     dict(lambda_log2=6, sigma=1, kappa=0),
     dict(table_init=1024), dict(trim=0), dict(seed=12345),
