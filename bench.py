@@ -30,10 +30,11 @@ WORKLOADS = {
     "knn_10M_k5": (2, "directed 5-NN graph of 1e7 points, mixture of 1000 isotropic Gaussians (sigma .01) "
                       "in the unit cube, ties to the lower id"),
     "grid10000_p0.5": (3, "2-D grid 10000x10000 (no wrap), each neighbour arc kept with p=0.5"),
-    "batched4096": (4, "4096 graphs, vertex counts log-uniform in [1e3, 1e5], family uniform in {torus p=0.5, "
-                       "R-MAT edge factor 8, 3-D k-NN k=5}, run as one disjoint union with an autotuned schedule"),
+    "batched4096": (4, "4096 graphs, vertex counts log-uniform in [1e3, 10^hi] (hi = --batch-hi, default 6), "
+                       "family uniform in {torus p=0.5, R-MAT edge factor 8, 3-D k-NN k=5}, run as one disjoint "
+                       "union with an autotuned schedule"),
 }
-BATCH_G, BATCH_LO, BATCH_HI, BATCH_SEED = 4096, 3.0, 5.0, 1004
+BATCH_G, BATCH_LO, BATCH_SEED = 4096, 3.0, 1004
 # the frontier kernels timed with options.timing, as rocprofv3 names them
 KERNEL_NAMES = ["hipscc::k_expand<0, 1>", "hipscc::k_expand<1, 1>", "hipscc::k_pull", "hipscc::k_expand_heavy<0>",
                 "hipscc::k_expand_heavy<1>", "hipscc::k_bag_extract"]
@@ -91,7 +92,13 @@ def run_batched(args, desc):
     from paper_2303_04934_amd import autotune
 
     t0 = time.perf_counter()
-    graphs = graphgen.batched(BATCH_G, BATCH_SEED, BATCH_LO, BATCH_HI)
+    spec = graphgen.batched_spec(BATCH_G, BATCH_SEED, BATCH_LO, args.batch_hi)
+    graphs = []
+    for i in range(0, BATCH_G, 256):  # generated in slices, with progress lines
+        graphs += graphgen.batched_slice(BATCH_G, BATCH_SEED, BATCH_LO, args.batch_hi, i, min(BATCH_G, i + 256))
+        print("[bench] generated %d/%d graphs (%.0f s)" % (len(graphs), BATCH_G, time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    assert len(graphs) == len(spec)
     vb, ab, oo, oa, io, ia = graphgen.concat(graphs)
     print("[bench] generated %d graphs, n=%d m=%d in %.1f s" % (len(graphs), vb[-1], ab[-1], time.perf_counter() - t0),
           file=sys.stderr, flush=True)
@@ -130,6 +137,7 @@ def run_batched(args, desc):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     loop_out = []
+    print("[bench] one scc_labels call per graph ...", file=sys.stderr, flush=True)
     for g in range(len(graphs)):
         n, lo = int(vb[g + 1] - vb[g]), int(vb[g]) + g
         dg = scc.DeviceGraph(n, int(ab[g + 1] - ab[g]), arrs[0][lo:lo + n + 1], arrs[1][int(ab[g]):int(ab[g + 1])],
@@ -146,7 +154,8 @@ def run_batched(args, desc):
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "batched4096", "description": desc, "graphs": len(graphs), "n": int(vb[-1]), "m": m,
-                   "seed": BATCH_SEED, "tau": opts.tau, "beta": opts.beta, "schedule": "autotuned"},
+                   "seed": BATCH_SEED, "size_exponents": [BATCH_LO, args.batch_hi], "tau": opts.tau,
+                   "beta": opts.beta, "schedule": "autotuned"},
         "batched_vs_plain": {"autotuned_batched_ms": dt * 1e3, "default_batched_ms": default_ms,
                              "per_graph_loop_ms": loop_ms, "loop_labels_identical": loop_same,
                              "autotune": tuned},
@@ -166,6 +175,9 @@ def run_batched(args, desc):
         ok = True
         for g, gr in enumerate(graphs):
             ok = ok and bool(np.array_equal(oracle.scc_graph(gr), got[vb[g]:vb[g + 1]]))
+            if g % 512 == 511:
+                print("[bench] oracle %d/%d graphs (%.0f s)" % (g + 1, len(graphs), time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
         t = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
                                 "sample": "every graph of the batch, sequential Tarjan oracle, %.1f s" % t}
@@ -186,6 +198,8 @@ def main():
     ap.add_argument("--cpu-runs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--policy", type=int, default=0, help="0 fixed budget, 1 learned per-round policy")
+    ap.add_argument("--batch-hi", type=float, default=6.0,
+                    help="batched workload: vertex counts log-uniform in [1e3, 10**batch_hi]")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()

@@ -221,8 +221,13 @@ def batched_spec(G: int = 4096, seed: int = 1004, lo_exp: float = 3.0, hi_exp: f
 
 def batched(G: int = 4096, seed: int = 1004, lo_exp: float = 3.0, hi_exp: float = 6.0):
     """List of Graphs for the batched workload (sizes log-uniform in 10**[lo,hi])."""
+    return batched_slice(G, seed, lo_exp, hi_exp, 0, G)
+
+
+def batched_slice(G: int, seed: int, lo_exp: float, hi_exp: float, g0: int, g1: int):
+    """Graphs g0..g1-1 of the batched workload (the same graphs batched() returns)."""
     out = []
-    for fam, n, gseed in batched_spec(G, seed, lo_exp, hi_exp):
+    for fam, n, gseed in batched_spec(G, seed, lo_exp, hi_exp)[g0:g1]:
         if fam == 0:
             rows = max(3, int(round(math.sqrt(n))))
             cols = max(3, int(round(n / rows)))
