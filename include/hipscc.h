@@ -89,6 +89,12 @@ typedef struct {
  *   trim         1 = remove vertices of zero in- or out-degree first (4.1).
  *   table_init   reach table slots for the first multi-source batch (power of
  *                two); 0 = the sizing heuristic of Section 4.5.
+ *   table_floor  the heuristic's floor as a fraction of the active vertices
+ *                (Section 4.5 uses 0.3); the other term is 1.5 x the previous
+ *                batch's pairs x the batch growth.  Default 1.2: a sparser
+ *                table means fewer linear-probing steps, each a dependent
+ *                load and CAS on the GPU, and HBM is plentiful; a smaller
+ *                floor risks restarts on a larger table.
  *   seeds_per_wave frontier entries a wavefront takes per fetch (1..64);
  *                0 = chosen from the frontier size.
  *   timing       bit mask over SCC_KERNEL_*: bit k brackets every launch of
@@ -131,7 +137,8 @@ typedef struct {
     int32_t arcs_per_lane;
     float vgc_fill;
     float beta_fast;
-    int32_t reserved[2];
+    float table_floor;
+    int32_t reserved[1];
 } scc_options_t;
 
 /* Frontier kernels timed with options.timing. */

@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("trim", ctypes.c_int32), ("table_init", ctypes.c_int64),
                 ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float),
-                ("beta_fast", ctypes.c_float), ("reserved", ctypes.c_int32 * 2)]
+                ("beta_fast", ctypes.c_float), ("table_floor", ctypes.c_float), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):

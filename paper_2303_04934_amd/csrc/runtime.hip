@@ -241,6 +241,7 @@ scc_options_t defaults() {
     o.tau = 2048;
     o.beta = 2.0f;
     o.beta_fast = 8.0f;
+    o.table_floor = 1.2f;
     o.lambda_log2 = 0;
     o.sigma = 50;
     o.kappa = 8;
@@ -270,6 +271,14 @@ uint32_t lam_log2_for(const scc_options_t &o, uint64_t entries) {
 }
 
 void check_opts(scc_ctx *c, const scc_options_t &o) {
+    if (!(o.table_floor >= 0.f) || !(o.table_floor <= 16.f)) {
+        set_err(c, "table_floor must be in [0, 16]");
+        throw Fail{SCC_EINVAL};
+    }
+    if (!(o.vgc_fill >= -1e6f && o.vgc_fill <= 1e6f) || !(o.beta_fast >= 0.f && o.beta_fast <= 1e6f)) {
+        set_err(c, "vgc_fill / beta_fast out of range");
+        throw Fail{SCC_EINVAL};
+    }
     if (o.arcs_per_lane != 0 && o.arcs_per_lane != 1 && o.arcs_per_lane != 2 && o.arcs_per_lane != 4) {
         set_err(c, "arcs_per_lane must be 0, 1, 2 or 4");
         throw Fail{SCC_EINVAL};
@@ -1005,7 +1014,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     // host's view of |V'| lags one batch behind (it is read at the next
     // check); it is only used as an upper bound.
     uint64_t pos = j1 < (uint32_t)n ? (uint64_t)j1 + 1 : (uint64_t)n;
-    double bsize = 1.0;
+    double bsize = 1.0, prev_bsize = 1.0;
     bool fast_next = false;
     const uint64_t lanes_all = (uint64_t)c->expand_grid[kMulti][0] * kBlock;
     int32_t epoch = 1;
@@ -1034,8 +1043,11 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         pos = p1;
         // Section 4.5: next table size = nextpow2(max(0.3 b, 1.5 a)), b = |V'|,
         // a = pairs found by the previous search in the same direction.
+        // (the pairs of the previous batch scale with the batch's growth)
+        const double growth = bsize / std::max(prev_bsize, 1.0);
+        prev_bsize = bsize;
         auto size_for = [&](uint64_t a) {
-            uint64_t want = (uint64_t)std::max(0.3 * (double)active, 1.5 * (double)a);
+            uint64_t want = (uint64_t)std::max((double)o.table_floor * (double)active, 1.5 * growth * (double)a);
             want = std::max<uint64_t>(want, 2 * kmax);
             want = std::max<uint64_t>(want, 1024);
             if (o.table_init > 0 && epoch == 1) want = (uint64_t)o.table_init;

@@ -83,7 +83,7 @@ def test_config0_full_size(gpu):
     dict(beta=1.1), dict(beta=1.5), dict(beta=8.0), dict(beta_fast=0.0), dict(beta_fast=64.0), dict(arcs_per_lane=1), dict(arcs_per_lane=2),
     dict(arcs_per_lane=1, tau=512, lambda_log2=10),
     dict(lambda_log2=6, sigma=1, kappa=0),
-    dict(table_init=1024), dict(trim=0), dict(seed=12345),
+    dict(table_init=1024), dict(trim=0), dict(seed=12345), dict(table_floor=0.0), dict(table_floor=0.3),
 ])
 def test_schedule_invariance(gpu, opt):
     g = graphgen.torus(100, 120, 0.55, seed=77)
