@@ -13,9 +13,12 @@ fixed budget, timed end to end, and traced (one feature row per round).
 Every traced row of a graph is labelled, for each class c, with the score
 -log(T(c) / min_c' T(c')), where T(c) is the graph's whole-run time with
 class c: the regret of that class on graphs whose rounds look like this one.
-The MLP regresses the four sparse-mode scores (the dense outputs are not
-trained: the frontier mode stays with the direction rule), so at run time
-it picks, round by round, the class that did best on rounds of that kind.
+The classes other than the default budget's lose a 3% margin, so the
+policy departs from the fixed schedule only where the traces show a clear
+win.  The MLP regresses the four sparse-mode scores (the dense outputs are
+not trained: the frontier mode stays with the direction rule), so at run
+time it picks, round by round, the class that did best on rounds of that
+kind.
 An earlier target, the round's own progress rate, was dominated by state
 noise and picked budgets that lost on every benchmark graph.  The policy
 only chooses schedules: the SCC labels do not depend on it.
@@ -162,10 +165,19 @@ def collect(repeats=4, verbose=True):
     return np.concatenate(rows), np.concatenate(gids), np.asarray(times)
 
 
-def scores_for(gids, times):
-    """Per-row class scores -log(T(c) / min T) of the row's graph."""
+DEFAULT_CLASS = 2   # the library's default budget (2048) is class 2
+MARGIN = 0.03       # another class must win by 3% to be preferred
+
+
+def scores_for(gids, times, margin=MARGIN):
+    """Per-row class scores -log(T(c) / min T) of the row's graph, with the
+    classes other than the default budget's lowered by `margin`, so that the
+    policy leaves the fixed schedule only where the traces show a clear win."""
     t = np.asarray(times, np.float64)
     sc = -np.log(t / t.min(axis=1, keepdims=True))
+    other = np.ones(sc.shape[1], bool)
+    other[DEFAULT_CLASS] = False
+    sc[:, other] -= margin
     return sc[np.asarray(gids)].astype(np.float32)
 
 
