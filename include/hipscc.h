@@ -108,11 +108,13 @@ typedef struct {
  *                per lane shorten the chain of dependent memory accesses of a
  *                step but cost registers, hence resident wavefronts.
  *   beta_fast    batches grow by beta_fast instead of beta after a cheap
- *                batch: its sources reached fewer than 4 vertices each (per
- *                direction) and its frontiers never exceeded the expand
- *                grid's lanes, so a larger batch costs little.  Any growth
- *                factor above 1 keeps Algorithm 1 correct.  Default 8;
- *                <= beta turns it off.
+ *                batch: its frontiers (degree sums seen at host checks)
+ *                never reached a sixteenth of the expand grid's lanes, or
+ *                its sources reached fewer than 4 vertices each (per
+ *                direction) and its frontiers never exceeded the lanes.  Its
+ *                rounds were latency bound, so a larger batch costs little.
+ *                Any growth factor above 1 keeps Algorithm 1 correct.
+ *                Default 8; <= beta turns it off.
  *   vgc_fill     local search runs in rounds whose frontier has fewer arcs
  *                (entries x average degree) than vgc_fill x the lanes of the
  *                expand grid; a frontier above that keeps the GPU busy on its

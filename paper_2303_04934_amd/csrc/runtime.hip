@@ -1100,9 +1100,12 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         const uint32_t k = c->hctl->sh.k;
         a_out = c->hctl->lane[0].claims + k;
         a_in = c->hctl->lane[1].claims + k;
-        // a cheap batch: its sources reached few vertices each and its
-        // frontiers never filled the GPU, so the next one may grow faster
-        fast_next = DP.peak_fdeg < lanes_all && k > 0 && (a_out + a_in) < (uint64_t)kCheapPairs * 2 * k;
+        // a cheap batch: its frontiers never used a sixteenth of the GPU's
+        // lanes (its rounds were latency bound), or its sources reached few
+        // vertices each and its frontiers never filled the GPU; the next
+        // batch may grow faster
+        fast_next = DP.peak_fdeg < lanes_all / 16 ||
+                    (DP.peak_fdeg < lanes_all && k > 0 && (a_out + a_in) < (uint64_t)kCheapPairs * 2 * k);
         active = (int64_t)n - trimmed - count_sum(c, &CountLine::fin);
         if (k == 0) continue;  // nothing was claimed; the tables are still clean
         if (st) {
