@@ -671,7 +671,9 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
             Lane &L = lanes[i];
             if (!L.live) continue;
             const RoundCtl &rc = c->hctl->lane[L.id];
-            if ((rc.err & kErrCapacity) || c->hctl->bag[L.id].overflow) {
+            const bool lane_full = (rc.err & kErrCapacity) || c->hctl->bag[L.id].overflow;
+            if (lane_full && L.mode != kMulti) {
+                // a single-source frontier holds each vertex at most once
                 set_err(c, "frontier capacity exceeded (err=%u, bag overflow=%u)", rc.err, c->hctl->bag[L.id].overflow);
                 throw Fail{SCC_EINTERNAL};
             }
@@ -688,7 +690,9 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
                     (float)(rc.claims - rc.snap_claims), (float)nf_new, (float)c->epoch, (float)P.n};
                 c->trace.insert(c->trace.end(), row, row + SCC_TRACE_FIELDS);
             }
-            if (L.mode == kMulti && (rc.err & kErrTable)) {
+            // a multi-source search whose reach table or frontier buffers ran
+            // out restarts with both doubled
+            if (L.mode == kMulti && ((rc.err & kErrTable) || lane_full)) {
                 if (P.st) P.st->rounds_multi += rc.rounds;  // rounds of the abandoned attempt
                 restart_multi(c, L, P);
                 L.fdeg = L.claims = 0;
@@ -1046,8 +1050,14 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         // (the pairs of the previous batch scale with the batch's growth)
         const double growth = bsize / std::max(prev_bsize, 1.0);
         prev_bsize = bsize;
+        // The pair term's growth is capped at 4 and the table at four times
+        // the active vertices plus the sources: a batch that finds more pairs
+        // restarts on a larger table, instead of every batch reserving tables
+        // (and the frontier bags sized from them) for the worst case.
         auto size_for = [&](uint64_t a) {
-            uint64_t want = (uint64_t)std::max((double)o.table_floor * (double)active, 1.5 * growth * (double)a);
+            uint64_t want = (uint64_t)std::max((double)o.table_floor * (double)active,
+                                               1.5 * std::min(growth, 4.0) * (double)a);
+            want = std::min<uint64_t>(want, 4 * (uint64_t)std::max<int64_t>(active, 0) + 2 * kmax);
             want = std::max<uint64_t>(want, 2 * kmax);
             want = std::max<uint64_t>(want, 1024);
             if (o.table_init > 0 && epoch == 1) want = (uint64_t)o.table_init;
@@ -1063,7 +1073,10 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         if (grew) fill_u64(c, c->Tin.p, c->Tin.cap, kEmpty64);
         c->tables_dirty = true;
         for (int d = 0; d < 2; d++)
-            ensure_lane(c, d, std::max<uint64_t>(d ? ts_in : ts_out, (uint64_t)n), c->bag_lam_log2);
+            // frontier buffers for one round's pairs: up to 2n (a search that
+            // needs more restarts with larger ones)
+            ensure_lane(c, d, std::max<uint64_t>(std::min<uint64_t>(d ? ts_in : ts_out, 2 * (uint64_t)n), (uint64_t)n),
+                        c->bag_lam_log2);
         resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_rs).count();
         SeedArgs SA;
         memset(&SA, 0, sizeof SA);
