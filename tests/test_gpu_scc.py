@@ -53,6 +53,20 @@ def test_degenerate_graphs(gpu):
     check_labels(gpu, graphgen.from_arcs(3, [0, 0, 1, 2, 2], [1, 1, 2, 0, 0]), name="multiarcs")
 
 
+@pytest.mark.parametrize("opt", [dict(), dict(table_floor=0.0, table_init=1024), dict(beta=8.0)])
+def test_quadratic_reach(gpu, opt):
+    # m 2-cycles (a_i, b_i) with arcs a_i -> a_j for every i < j: each source
+    # reaches every later cycle in one hop, so a batch of k sources puts about
+    # k*m/2 pairs into its first round's frontier, far above the vertex count;
+    # reach tables and frontier buffers overflow and the searches restart
+    m = 400
+    i, j = np.triu_indices(m, 1)
+    src = np.concatenate([np.arange(m), np.arange(m) + m, i])
+    dst = np.concatenate([np.arange(m) + m, np.arange(m), j])
+    g = graphgen.from_arcs(2 * m, src, dst)
+    check_labels(gpu, g, gpu.default_options(**opt), name="cycle-dag m=%d %s" % (m, opt))
+
+
 def test_empty_graph(gpu):
     import torch
     say("empty graph")
