@@ -255,17 +255,23 @@ __global__ void k_first_active(Perm P, uint32_t p0, uint32_t p1, const int32_t *
 // falls in [p0, p1).  Reading every label in order costs 4n bytes, less than
 // gathering the range's labels in random order once the range exceeds about
 // n/16 positions (one cache sector per position).
+// The inverse permutation is computed once per call: the first scan (build)
+// inverts every vertex and stores the positions in invp, later scans read them.
 __global__ void k_select_scan(Perm P, uint32_t p0, uint32_t p1, int32_t n, const int32_t *label, int32_t *srcvert,
-                              int32_t *srclab, Shared *sh) {
+                              int32_t *srclab, Shared *sh, uint32_t *invp, bool build) {
     for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = v0 + threadIdx.x;
         int32_t l = -1;
         if (v < n) {
             l = label[v];
-            if (l >= 0) {
-                const uint32_t j = perm_invert(P, (uint32_t)v);
-                if (j < p0 || j >= p1) l = -1;
+            uint32_t j = 0;
+            if (build) {
+                j = perm_invert(P, (uint32_t)v);
+                invp[v] = j;
+            } else if (l >= 0) {
+                j = invp[v];
             }
+            if (l >= 0 && (j < p0 || j >= p1)) l = -1;
         }
         const bool act = l >= 0;
         const uint64_t m = ballot(act);
@@ -1144,9 +1150,12 @@ __global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, const Shar
 // Multi source, pass 1: accumulate the per-vertex set hashes of R_out (pairs
 // of the forward table) and R_in (backward table), and detect vertices that
 // share a source in both directions (Algorithm 1: R_1 and R_2 intersect).
-__global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, const uint64_t *Tin, uint64_t min_,
+// With clear_in the backward table's slots are emptied as they are read (no
+// thread of this pass probes that table; the dense relabel that follows does
+// not read it).
+__global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, uint64_t *Tin, uint64_t min_,
                              uint32_t limit, const int32_t *srcvert, unsigned long long *sig_out,
-                             unsigned long long *sig_in, int32_t *fin) {
+                             unsigned long long *sig_in, int32_t *fin, bool clear_in) {
     const uint64_t n_out = mout + 1, n_tot = n_out + min_ + 1;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_tot; i += (uint64_t)gridDim.x * blockDim.x) {
         if (i < n_out) {
@@ -1156,6 +1165,7 @@ __global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, const uint64_t
         } else {
             const uint64_t key = Tin[i - n_out];
             if (key == kEmpty64) continue;
+            if (clear_in) Tin[i - n_out] = kEmpty64;
             const int32_t v = key_vertex(key);
             atomicAdd(&sig_in[v], (unsigned long long)sig_term_in(srcvert[key_source(key)]));
             if (table_contains(Tout, mout, limit, key)) atomicMin(&fin[v], (int32_t)key_source(key));
@@ -1184,6 +1194,38 @@ __global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, ui
             cnt++;
         } else {
             label[v] = relabel_hash(label[v], sig_in[v], sig_out[v]);
+        }
+        sig_in[v] = 0;
+        sig_out[v] = 0;
+        fin[v] = kInf32;
+    }
+    block_add_u32(&cs->s[blockIdx.x % kStripes].fin, cnt);
+}
+
+// Multi source, pass 2 for batches whose pairs are a sizeable fraction of the
+// vertices: the same relabelling as k_relabel_multi, taken per vertex in one
+// coalesced pass instead of per table slot with an owner election (a vertex
+// was touched iff its accumulators are set; finished vertices are never
+// claimed).  The forward table is cleared here, the backward one was cleared
+// by k_accumulate.
+__global__ void k_relabel_dense(int32_t n, uint64_t *Tout, uint64_t mout, const int32_t *srcvert,
+                                unsigned long long *sig_out, unsigned long long *sig_in, int32_t *fin, int32_t *label,
+                                CountStripes *cs) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= mout; i += stride) Tout[i] = kEmpty64;
+    uint32_t cnt = 0;
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < (uint64_t)n; v += stride) {
+        const int32_t l = label[v];
+        if (l < 0) continue;
+        const int32_t f = fin[v];
+        const unsigned long long si = sig_in[v], so = sig_out[v];
+        if (f != kInf32) {
+            label[v] = ~srcvert[f];
+            cnt++;
+        } else if ((si | so) != 0ull) {
+            label[v] = relabel_hash(l, si, so);
+        } else {
+            continue;
         }
         sig_in[v] = 0;
         sig_out[v] = 0;

@@ -54,6 +54,7 @@ constexpr int kTimedMax = 4 * kMaxSlots;  // timed launches between host checks
 constexpr int kPhases = 5;      // trim, first, multi, resize, label
 constexpr uint32_t kProbeLimit = 128;
 constexpr uint64_t kCheapPairs = 4;  // reach pairs per source of a batch that counts as cheap
+constexpr uint64_t kDenseLabelDiv = 8;  // relabel per vertex once a batch has n / 8 pairs
 
 }  // namespace
 
@@ -69,6 +70,7 @@ struct scc_ctx {
     std::string err;
 
     DevBuf<int32_t> label, aux, stamp, srcvert, srclab, fin;
+    DevBuf<uint32_t> invp;          // inverse vertex permutation (large source batches)
     DevBuf<unsigned long long> sig_out, sig_in;
     DevBuf<uint32_t> vis[2];        // visited bitmaps of the two single-source lanes
     DevBuf<uint32_t> bm[2][2];      // front/next bitmaps per lane (dense mode)
@@ -1022,6 +1024,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     bool fast_next = false;
     const uint64_t lanes_all = (uint64_t)c->expand_grid[kMulti][0] * kBlock;
     int32_t epoch = 1;
+    bool invp_built = false;  // the inverse permutation of this call's P is stored
     uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0;
     int64_t active = (int64_t)n - trimmed;  // upper bound
     while (active > 0 && pos < (uint64_t)n) {
@@ -1036,9 +1039,13 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kBlock), 0, c->stream, sh, &c->dctl->lane[0], &c->dctl->lane[1]);
         LAUNCHCHK("k_batch_reset");
         if ((p1 - pos) * 16 > (uint64_t)n) {
+            const bool build = !invp_built;
+            if (build) ensure(c, c->invp, (uint64_t)n);
             hipLaunchKernelGGL(k_select_scan, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, P,
-                               (uint32_t)pos, (uint32_t)p1, n, c->label.p, c->srcvert.p, c->srclab.p, sh);
+                               (uint32_t)pos, (uint32_t)p1, n, c->label.p, c->srcvert.p, c->srclab.p, sh, c->invp.p,
+                               build);
             LAUNCHCHK("k_select_scan");
+            invp_built = true;
         } else {
             hipLaunchKernelGGL(k_select_sources, dim3(grid_for(c, p1 - pos)), dim3(kBlock), 0, c->stream, P,
                                (uint32_t)pos, (uint32_t)p1, c->label.p, c->srcvert.p, c->srclab.p, sh);
@@ -1127,13 +1134,24 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         }
         phase_begin(c, 4, ph);
         const uint64_t tot = ts_out + ts_in;
+        // a batch with many pairs relabels per vertex (one coalesced pass),
+        // a small one per table slot (random accesses to the touched vertices)
+        const bool dense_label = (a_out + a_in) * kDenseLabelDiv >= (uint64_t)n;
         hipLaunchKernelGGL(k_accumulate, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
-                           c->Tin.p, ts_in - 1, kProbeLimit, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p);
+                           c->Tin.p, ts_in - 1, kProbeLimit, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p,
+                           dense_label);
         LAUNCHCHK("k_accumulate");
-        hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
-                           c->Tin.p, ts_in - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p, c->stamp.p, epoch,
-                           c->label.p, &c->dctl->cs);
-        LAUNCHCHK("k_relabel_multi");
+        if (dense_label) {
+            hipLaunchKernelGGL(k_relabel_dense, dim3(grid_for(c, std::max<uint64_t>(ts_out, (uint64_t)n))), dim3(kBlock),
+                               0, c->stream, n, c->Tout.p, ts_out - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p,
+                               c->fin.p, c->label.p, &c->dctl->cs);
+            LAUNCHCHK("k_relabel_dense");
+        } else {
+            hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p,
+                               ts_out - 1, c->Tin.p, ts_in - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p,
+                               c->stamp.p, epoch, c->label.p, &c->dctl->cs);
+            LAUNCHCHK("k_relabel_multi");
+        }
         phase_end(c, ph);
         epoch++;
     }
@@ -1351,7 +1369,7 @@ void scc_destroy(scc_ctx_t *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    release(c->label); release(c->aux); release(c->stamp); release(c->srcvert); release(c->srclab);
+    release(c->label); release(c->aux); release(c->stamp); release(c->invp); release(c->srcvert); release(c->srclab);
     release(c->fin); release(c->sig_out); release(c->sig_in);
     for (int i = 0; i < 2; i++) {
         release(c->vis[i]); release(c->bm[i][0]); release(c->bm[i][1]);
