@@ -107,7 +107,8 @@ def run_batched(args, desc):
     base = scc.default_options(validate=0)
     t0 = time.perf_counter()
     opts, tuned = autotune.tune(vb, ab, *arrs, base_options=base)
-    print("[bench] autotune picked tau=%d beta=%.1f in %.1f s" % (opts.tau, opts.beta, time.perf_counter() - t0),
+    print("[bench] autotune picked tau=%d beta=%.1f beta_fast=%.0f in %.1f s" % (opts.tau, opts.beta, opts.beta_fast,
+                                                                           time.perf_counter() - t0),
           file=sys.stderr, flush=True)
     # warm-up; its last call times every frontier kernel to pick the dominant one
     for i in range(max(args.warmup, 1)):
@@ -155,7 +156,7 @@ def run_batched(args, desc):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "batched4096", "description": desc, "graphs": len(graphs), "n": int(vb[-1]), "m": m,
                    "seed": BATCH_SEED, "size_exponents": [BATCH_LO, args.batch_hi], "tau": opts.tau,
-                   "beta": opts.beta, "schedule": "autotuned"},
+                   "beta": opts.beta, "beta_fast": opts.beta_fast, "schedule": "autotuned"},
         "batched_vs_plain": {"autotuned_batched_ms": dt * 1e3, "default_batched_ms": default_ms,
                              "per_graph_loop_ms": loop_ms, "loop_labels_identical": loop_same,
                              "autotune": tuned},

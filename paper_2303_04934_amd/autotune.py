@@ -1,13 +1,14 @@
 """Schedule autotuner for batched SCC runs.
 
 A batch of many graphs runs as one disjoint union (``scc_labels_batched``),
-so one schedule -- the local-search budget tau (Section 3.2) and the
-prefix-doubling multiplier beta (Algorithm 1) -- serves every graph of it.
-Neither changes the labels, only rounds and work, and the best values
-depend on the graphs (long-diameter lattices want large tau and beta, k-NN
-graphs smaller ones) and on the batch's size: beta sets how many source
-batches a run takes, log_beta(n), so a sample must keep the scale of the
-whole batch.  The tuner times a few candidate schedules on a sample of the
+so one schedule -- the local-search budget tau (Section 3.2), the
+prefix-doubling multiplier beta (Algorithm 1) and the faster multiplier
+beta_fast used after latency-bound source batches -- serves every graph of
+it.  None of them changes the labels, only rounds and work, and the best
+values depend on the graphs (k-NN graphs and short-diameter graphs gain from
+fast batch growth, long lattices lose) and on the batch's size: beta sets how
+many source batches a run takes, log_beta(n), so a sample must keep the
+scale of the whole batch.  The tuner times a few candidate schedules on a sample of the
 batch (every k-th graph; by default every second one), on the GPU, and
 returns the fastest as options for the whole batch.
 
@@ -22,8 +23,9 @@ import numpy as np
 
 from . import _native
 
-# candidate (tau, beta) pairs: the defaults first, then larger rounds and batches
-CANDIDATES = [(2048, 2.0), (4096, 2.0), (2048, 3.0), (8192, 3.0), (1024, 2.0), (4096, 4.0)]
+# candidate (tau, beta, beta_fast) schedules: the defaults first
+CANDIDATES = [(2048, 2.0, 8.0), (2048, 2.0, 24.0), (4096, 2.0, 8.0), (2048, 3.0, 8.0), (4096, 2.0, 24.0),
+              (1024, 2.0, 16.0)]
 
 
 def _subset(vb, ab, arrays, idx):
@@ -49,8 +51,8 @@ def _subset(vb, ab, arrays, idx):
 
 def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = None, repeats: int = 1,
          candidates=CANDIDATES, base_options=None, verbose: bool = False):
-    """Pick (tau, beta) for a batch.  Returns (options, report) where report
-    lists each candidate's best sample time in ms."""
+    """Pick (tau, beta, beta_fast) for a batch.  Returns (options, report)
+    where report lists each candidate's best sample time in ms."""
     import torch
 
     from . import default_options, scc_labels_batched
@@ -65,10 +67,11 @@ def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = Non
     svb, sab, sarr = _subset(vb, ab, (out_off, out_adj, in_off, in_adj), idx)
     report = []
     best = None
-    for tau, beta in candidates:
+    for tau, beta, beta_fast in candidates:
         o = default_options() if base_options is None else _copy(base_options)
         o.tau = tau
         o.beta = beta
+        o.beta_fast = beta_fast
         o.timing = 0
         ts = []
         for r in range(repeats + 1):
@@ -79,14 +82,15 @@ def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = Non
             if r:  # the first call warms up (allocations)
                 ts.append((time.perf_counter() - t0) * 1e3)
         ms = min(ts)
-        report.append({"tau": tau, "beta": beta, "sample_ms": ms})
+        report.append({"tau": tau, "beta": beta, "beta_fast": beta_fast, "sample_ms": ms})
         if verbose:
-            print("[autotune] tau=%d beta=%.1f sample %.2f ms" % (tau, beta, ms), flush=True)
+            print("[autotune] tau=%d beta=%.1f beta_fast=%.0f sample %.2f ms" % (tau, beta, beta_fast, ms),
+                  flush=True)
         if best is None or ms < best[0]:
-            best = (ms, tau, beta)
+            best = (ms, tau, beta, beta_fast)
     o = default_options() if base_options is None else _copy(base_options)
     if best is not None:
-        o.tau, o.beta = best[1], best[2]
+        o.tau, o.beta, o.beta_fast = best[1], best[2], best[3]
     return o, {"sample_graphs": len(idx), "sample_arcs": int(sab[-1]) if len(idx) else 0, "candidates": report}
 
 

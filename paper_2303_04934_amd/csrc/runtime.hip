@@ -63,6 +63,7 @@ struct scc_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int num_cu = 256;
+    uint64_t table_slots_max = 1ull << 24;  // cap of the estimated reach-table size (set from device memory)
     int expand_blocks = 2048;
     int expand_grid[2][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
     int arcs_per_lane = 1;          // options.arcs_per_lane of the current call
@@ -1057,15 +1058,17 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         // (the pairs of the previous batch scale with the batch's growth)
         const double growth = bsize / std::max(prev_bsize, 1.0);
         prev_bsize = bsize;
-        // The pair term's growth is capped at 4 and the table at four times
-        // the active vertices plus the sources: a batch that finds more pairs
-        // restarts on a larger table, instead of every batch reserving tables
-        // (and the frontier bags sized from them) for the worst case.
+        // The table stops at eight times the active vertices plus the
+        // sources (and at a fixed share of device memory): a batch that finds
+        // more pairs restarts on a larger table, instead of every batch
+        // reserving tables (and the frontier bags sized from them) for the
+        // worst case.
         auto size_for = [&](uint64_t a) {
             uint64_t want = (uint64_t)std::max((double)o.table_floor * (double)active,
-                                               1.5 * std::min(growth, 4.0) * (double)a);
-            want = std::min<uint64_t>(want, 4 * (uint64_t)std::max<int64_t>(active, 0) + 2 * kmax);
+                                               1.5 * growth * (double)a);
+            want = std::min<uint64_t>(want, 8 * (uint64_t)std::max<int64_t>(active, 0) + 2 * kmax);
             want = std::max<uint64_t>(want, 2 * kmax);
+            want = std::min<uint64_t>(want, c->table_slots_max);
             want = std::max<uint64_t>(want, 1024);
             if (o.table_init > 0 && epoch == 1) want = (uint64_t)o.table_init;
             return next_pow2(want);
@@ -1333,6 +1336,14 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
         hipDeviceProp_t prop;
         HIPCHK(hipGetDeviceProperties(&prop, device));
         c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        // a reach table's estimated size stops at the largest power of two
+        // within 1/16 of device memory (2^31 slots, 16 GiB, on a 288 GB
+        // device); a search that needs more grows it by restarting
+        {
+            uint64_t slots = 1024;
+            while (slots * 2 * sizeof(uint64_t) * 16 <= (uint64_t)prop.totalGlobalMem) slots *= 2;
+            c->table_slots_max = slots;
+        }
         int nb = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand<kMulti, 1>, kBlock, 0));
         if (nb < 1) nb = 1;
