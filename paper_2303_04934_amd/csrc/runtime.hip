@@ -600,7 +600,11 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
         L.avg_deg = P.n > 0 ? std::max(1.0, (double)P.m / (double)P.n) : 1.0;
         L.policy_primed = false;
     }
-    const uint64_t arcs_on = (uint64_t)std::max<int64_t>(P.m / 14, 1);
+    // direction-optimising switch (single-source searches): dense once the
+    // frontier's arcs exceed m / 28 (a pull round is a coalesced pass, so the
+    // switch comes earlier than the CPU rule's m / 14), sparse again below
+    // |V'| / 24 frontier vertices
+    const uint64_t arcs_on = (uint64_t)std::max<int64_t>(P.m / 28, 1);
     const int64_t back_off = std::max<int64_t>(P.nsub / 24, 1);
     // rounds between host checks: they double while nothing needs watching.
     // Multi-source searches start at 2, which saves a check on the many
