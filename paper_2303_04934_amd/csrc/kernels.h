@@ -256,7 +256,9 @@ __global__ void k_first_active(Perm P, uint32_t p0, uint32_t p1, const int32_t *
 // gathering the range's labels in random order once the range exceeds about
 // n/16 positions (one cache sector per position).
 // The inverse permutation is computed once per call: the first scan (build)
-// inverts every vertex and stores the positions in invp, later scans read them.
+// inverts every active vertex and stores its position in invp, later scans
+// read them.  A finished vertex never becomes active again, so the vertices a
+// later scan asks for are a subset of those the build stored.
 __global__ void k_select_scan(Perm P, uint32_t p0, uint32_t p1, int32_t n, const int32_t *label, int32_t *srcvert,
                               int32_t *srclab, Shared *sh, uint32_t *invp, bool build) {
     for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
@@ -265,11 +267,13 @@ __global__ void k_select_scan(Perm P, uint32_t p0, uint32_t p1, int32_t n, const
         if (v < n) {
             l = label[v];
             uint32_t j = 0;
-            if (build) {
-                j = perm_invert(P, (uint32_t)v);
-                invp[v] = j;
-            } else if (l >= 0) {
-                j = invp[v];
+            if (l >= 0) {
+                if (build) {
+                    j = perm_invert(P, (uint32_t)v);
+                    invp[v] = j;
+                } else {
+                    j = invp[v];
+                }
             }
             if (l >= 0 && (j < p0 || j >= p1)) l = -1;
         }

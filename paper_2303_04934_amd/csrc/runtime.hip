@@ -86,6 +86,11 @@ struct scc_ctx {
     DevBuf<int32_t> ubuf;           // batched: union CSR scratch
     uint32_t salt = 1;
     bool tables_dirty = false;      // a failed call may leave claims behind
+    // stamp/fin/sig_in/sig_out are known clean on [0, vclean_n) (zero sums,
+    // no finish mark, stamps below stamp_next): each batch's relabel leaves
+    // them so, and a call that ends normally starts the next one clean
+    int64_t vclean_n = 0;
+    int32_t stamp_next = 1;
     // options.timing: events around frontier-kernel launches
     uint32_t timing = 0;            // options.timing: bit k times kernel k (SCC_KERNEL_*)
     hipEvent_t tev[kTimedMax][2] = {};  // timed launches since the last host check
@@ -576,7 +581,7 @@ void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
 // Runs seeded lanes until every frontier is empty.
 //
 // Single-source lanes switch between sparse and dense rounds (Section 4.2)
-// by Beamer's rule: dense once the frontier's arcs exceed m / 14, sparse again
+// by Beamer's rule: dense once the frontier's arcs exceed m / 28, sparse again
 // once the frontier has fewer than nsub / 24 vertices (options.dense forces
 // either mode).  A lane near the switch is checked every round; otherwise
 // rounds go in blocks of K (doubling up to 64) between checks.  Each round
@@ -873,14 +878,16 @@ void check_graph_args(scc_ctx *c, const scc_graph_t *g) {
 
 // Per-vertex device state sized for n vertices.
 void ensure_vertex_state(scc_ctx *c, int64_t n) {
+    bool g[4] = {false, false, false, false};
     ensure(c, c->label, (uint64_t)n);
     ensure(c, c->aux, (uint64_t)n);
-    ensure(c, c->stamp, (uint64_t)n);
-    ensure(c, c->fin, (uint64_t)n);
+    ensure(c, c->stamp, (uint64_t)n, &g[0]);
+    ensure(c, c->fin, (uint64_t)n, &g[1]);
     ensure(c, c->srcvert, (uint64_t)n);
     ensure(c, c->srclab, (uint64_t)n);
-    ensure(c, c->sig_out, (uint64_t)n);
-    ensure(c, c->sig_in, (uint64_t)n);
+    ensure(c, c->sig_out, (uint64_t)n, &g[2]);
+    ensure(c, c->sig_in, (uint64_t)n, &g[3]);
+    if (g[0] || g[1] || g[2] || g[3]) c->vclean_n = 0;  // new memory holds anything
     for (int i = 0; i < 2; i++) {
         ensure(c, c->vis[i], (uint64_t)n / 32 + 2);
         ensure(c, c->bm[i][0], (uint64_t)n / 32 + 2);
@@ -942,12 +949,19 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     const bool ph = st != nullptr;
     ensure_vertex_state(c, n);
     if (o.validate) validate_graph(c, g);
-    // per-call state
+    // per-call state: the relabel accumulators and stamps are cleared only
+    // when the previous call did not leave them clean on [0, n)
     phase_begin(c, 4, ph);
-    fill_u32(c, (uint32_t *)c->stamp.p, (uint64_t)n, 0u);
-    fill_u32(c, (uint32_t *)c->fin.p, (uint64_t)n, (uint32_t)kInf32);
-    fill_u64(c, (uint64_t *)c->sig_out.p, (uint64_t)n, 0ull);
-    fill_u64(c, (uint64_t *)c->sig_in.p, (uint64_t)n, 0ull);
+    int64_t clean_after = std::max<int64_t>(c->vclean_n, n);
+    if (c->vclean_n < n || c->stamp_next > (1 << 30)) {
+        fill_u32(c, (uint32_t *)c->stamp.p, (uint64_t)n, 0u);
+        fill_u32(c, (uint32_t *)c->fin.p, (uint64_t)n, (uint32_t)kInf32);
+        fill_u64(c, (uint64_t *)c->sig_out.p, (uint64_t)n, 0ull);
+        fill_u64(c, (uint64_t *)c->sig_in.p, (uint64_t)n, 0ull);
+        c->stamp_next = 1;
+        clean_after = n;
+    }
+    c->vclean_n = 0;  // until this call ends normally
     for (int i = 0; i < 2; i++) {
         ensure_lane(c, i, (uint64_t)n, lam_log2_for(o, (uint64_t)n));
         reset_bag(c, i);
@@ -1029,6 +1043,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     bool fast_next = false;
     const uint64_t lanes_all = (uint64_t)c->expand_grid[kMulti][0] * kBlock;
     int32_t epoch = 1;
+    int32_t stamp_ep = c->stamp_next;  // owner-election stamp of the current batch
     bool invp_built = false;  // the inverse permutation of this call's P is stored
     uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0;
     int64_t active = (int64_t)n - trimmed;  // upper bound
@@ -1156,12 +1171,14 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         } else {
             hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p,
                                ts_out - 1, c->Tin.p, ts_in - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p,
-                               c->stamp.p, epoch, c->label.p, &c->dctl->cs);
+                               c->stamp.p, stamp_ep, c->label.p, &c->dctl->cs);
             LAUNCHCHK("k_relabel_multi");
         }
         phase_end(c, ph);
         epoch++;
+        stamp_ep++;
     }
+    c->stamp_next = stamp_ep;
     // ---- canonical labels: min vertex id per SCC
     phase_begin(c, 4, ph);
     hipLaunchKernelGGL(k_iota, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->aux.p);
@@ -1193,6 +1210,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         fill_counters(c, st, n);
     }
     c->tables_dirty = false;
+    c->vclean_n = clean_after;
 }
 
 // sources check for scc_reach: in range, label >= 0, distinct (stamp epoch)
@@ -1445,6 +1463,9 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
         GraphDev gd{g->n, g->m, g->out_off, g->out_adj, g->in_off, g->in_adj};
         ensure_vertex_state(c, n);
         if (o.validate) validate_graph(c, gd);
+        // the source check stamps with its own epochs: the next labelling
+        // call clears the vertex state again
+        c->vclean_n = 0;
         fill_u32(c, (uint32_t *)c->stamp.p, (uint64_t)n, 0u);
         Shared *sh = &c->dctl->sh;
         fill_u32(c, &sh->bad, 1, 0u);
