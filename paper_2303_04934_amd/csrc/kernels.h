@@ -210,13 +210,28 @@ __device__ __forceinline__ unsigned long long block_flush_ctr(unsigned long long
 // ------------------------------------------------------------------ trim ----
 // Section 4.1: a vertex with zero in- or out-degree is a singleton SCC.
 // Finished vertices store ~key (negative); key = v here.
+// It also writes the first search's visited bitmaps (both directions): the
+// trimmed vertices are the ones outside its subproblem (label 0), so they are
+// pre-set; the source's own bit is set when it is seeded.  A wave covers 64
+// consecutive vertices, i.e. two bitmap words.
 __global__ void k_trim(int32_t n, const int32_t *out_off, const int32_t *in_off, int32_t *label, int32_t do_trim,
-                       CountStripes *cs) {
+                       uint32_t *vis0, uint32_t *vis1, CountStripes *cs) {
     uint32_t cnt = 0;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const bool t = do_trim && (out_off[v + 1] == out_off[v] || in_off[v + 1] == in_off[v]);
-        label[v] = t ? ~(int32_t)v : 0;
-        cnt += t;
+    const int lane = lane_id();
+    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        bool t = true;  // past the end: blocked
+        if (v < n) {
+            t = do_trim && (out_off[v + 1] == out_off[v] || in_off[v + 1] == in_off[v]);
+            label[v] = t ? ~(int32_t)v : 0;
+            cnt += t;
+        }
+        const uint64_t m = ballot(t);
+        if ((lane == 0 || lane == 32) && v < n) {
+            const uint32_t bits = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
+            vis0[v >> 5] = bits;
+            vis1[v >> 5] = bits;
+        }
     }
     block_add_u32(&cs->s[blockIdx.x % kStripes].trimmed, cnt);
 }
@@ -372,11 +387,14 @@ __global__ void k_premark(int32_t n, const int32_t *label, int32_t L, int32_t s_
 }
 
 __global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_t *F, RoundCtl *rc,
-                              LaneStripes *ls) {
+                              LaneStripes *ls, uint32_t *vis) {
     if (blockIdx.x == 0) stripes_clear(ls);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const int32_t s = single_source(s_fixed, sh, P);
-        if (s >= 0) F[0] = pair_key(s, 0);
+        if (s >= 0) {
+            F[0] = pair_key(s, 0);
+            vis[s >> 5] |= 1u << (s & 31);  // the source is claimed up front
+        }
         rc->nF[0] = s >= 0 ? 1u : 0u;
         rc->nF[1] = 0;
         rc->heavy_n[0] = rc->heavy_n[1] = 0;
@@ -1258,14 +1276,21 @@ __global__ __launch_bounds__(kBlock) void k_canon_min(int32_t n, const int32_t *
         hv[i] = kInf32;
     }
     __syncthreads();
+    const int lane = lane_id();
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t l = label[v];
-        if (l >= 0 || ~l >= n) {
-            atomicOr(err, kErrUnfinished);
-            continue;
-        }
+        const bool bad = l >= 0 || ~l >= n;
+        if (bad) atomicOr(err, kErrUnfinished);
         const int32_t key = ~l;
-        if (v >= key) continue;
+        const bool want = !bad && v < key;
+        // a wave's vertices are consecutive, so among its lanes with the key
+        // of its lowest wanting lane, that lane holds the smallest id: the
+        // others have nothing to add (the members of a giant SCC often fill
+        // much of a wave)
+        const uint64_t wm = ballot(want);
+        if (!want) continue;
+        const int L0 = __builtin_ctzll(wm);
+        if (lane != L0 && key == wave_bcast(key, L0)) continue;
         const int slot = (int)(mix64((uint64_t)key) & (H - 1));
         const int32_t prev = atomicCAS(&hk[slot], -1, key);
         if (prev == -1 || prev == key) atomicMin(&hv[slot], (int32_t)v);

@@ -972,7 +972,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     phase_begin(c, 0, ph);
     Shared *sh = &c->dctl->sh;
     hipLaunchKernelGGL(k_trim, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g.out_off, g.in_off,
-                       c->label.p, o.trim ? 1 : 0, &c->dctl->cs);
+                       c->label.p, o.trim ? 1 : 0, c->vis[0].p, c->vis[1].p, &c->dctl->cs);
     LAUNCHCHK("k_trim");
     Perm P;
     P.n = (uint32_t)n;
@@ -998,11 +998,9 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     phase_begin(c, 1, ph);
     Lane L[2];
     for (int d = 0; d < 2; d++) {
-        hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p, 0, -1,
-                           sh, P, c->vis[d].p);
-        LAUNCHCHK("k_premark");
+        // the visited bitmaps were pre-set by the trimming pass
         hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, -1, sh, P, c->F[d].p, &c->dctl->lane[d],
-                           &c->dctl->ls[d]);
+                           &c->dctl->ls[d], c->vis[d].p);
         LAUNCHCHK("k_seed_single");
         L[d].id = d;
         L[d].mode = kSingle;
@@ -1502,7 +1500,7 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
             hipLaunchKernelGGL(k_premark, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, labels, lab, s,
                                sh, P0, c->vis[0].p);
             hipLaunchKernelGGL(k_seed_single, dim3(1), dim3(64), 0, c->stream, s, sh, P0, c->F[0].p, &c->dctl->lane[0],
-                               &c->dctl->ls[0]);
+                               &c->dctl->ls[0], c->vis[0].p);
             LAUNCHCHK("k_seed_single");
             L.mode = kSingle;
             L.S = make_search(c, 0, o, kSingle);
