@@ -274,53 +274,110 @@ __global__ void k_first_active(Perm P, uint32_t p0, uint32_t p1, const int32_t *
 // inverts every active vertex and stores its position in invp, later scans
 // read them.  A finished vertex never becomes active again, so the vertices a
 // later scan asks for are a subset of those the build stored.
-__global__ void k_select_scan(Perm P, uint32_t p0, uint32_t p1, int32_t n, const int32_t *label, int32_t *srcvert,
-                              int32_t *srclab, Shared *sh, uint32_t *invp, bool build) {
-    for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = v0 + threadIdx.x;
-        int32_t l = -1;
-        if (v < n) {
-            l = label[v];
-            uint32_t j = 0;
-            if (l >= 0) {
-                if (build) {
-                    j = perm_invert(P, (uint32_t)v);
-                    invp[v] = j;
-                } else {
-                    j = invp[v];
+// Output slots come from one counter (the batch's source count), and
+// same-address atomics serialise (about 11 ns each on MI355X), so a block
+// reserves once per kScanPer x 256 vertices: each thread keeps the labels of
+// its kScanPer vertices in registers until the block's reservation is made.
+constexpr int kScanPer = 16;
+__global__ __launch_bounds__(kBlock) void k_select_scan(Perm P, uint32_t p0, uint32_t p1, int32_t n,
+                                                        const int32_t *label, int32_t *srcvert, int32_t *srclab,
+                                                        Shared *sh, uint32_t *invp, bool build) {
+    __shared__ uint32_t part[kWavesPerBlock];
+    __shared__ uint32_t base_s;
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    const int64_t tile = (int64_t)kBlock * kScanPer;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < n; t0 += (int64_t)gridDim.x * tile) {
+        int32_t lab[kScanPer];
+        uint32_t act = 0;
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            const int64_t v = t0 + (int64_t)r * kBlock + threadIdx.x;
+            int32_t l = -1;
+            if (v < n) {
+                l = label[v];
+                if (l >= 0) {
+                    uint32_t j;
+                    if (build) {
+                        j = perm_invert(P, (uint32_t)v);
+                        invp[v] = j;
+                    } else {
+                        j = invp[v];
+                    }
+                    if (j < p0 || j >= p1) l = -1;
                 }
             }
-            if (l >= 0 && (j < p0 || j >= p1)) l = -1;
+            lab[r] = l;
+            act |= (l >= 0 ? 1u : 0u) << r;
         }
-        const bool act = l >= 0;
-        const uint64_t m = ballot(act);
-        const uint32_t base = block_reserve(&sh->k, (uint32_t)popc64(m));
-        if (act) {
-            const uint32_t idx = base + rank_below(m);
-            srcvert[idx] = (int32_t)v;
-            srclab[idx] = l;
+        const int cnt = __popc(act);
+        const int incl = wave_incl_scan(cnt);
+        if (lane == kWave - 1) part[wv] = (uint32_t)incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tsum = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) tsum += part[w];
+            base_s = tsum ? atomicAdd(&sh->k, tsum) : 0u;
+        }
+        __syncthreads();
+        uint32_t pos = base_s + (uint32_t)(incl - cnt);
+        for (int w = 0; w < wv; w++) pos += part[w];
+        __syncthreads();  // part/base_s are rewritten next iteration
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            if ((act >> r) & 1u) {
+                srcvert[pos] = (int32_t)(t0 + (int64_t)r * kBlock + threadIdx.x);
+                srclab[pos] = lab[r];
+                pos++;
+            }
         }
     }
 }
 
 // Sources of one batch: the active vertices among permutation positions
-// [p0, p1) (Algorithm 1: F = P_i intersect V').
-__global__ void k_select_sources(Perm P, uint32_t p0, uint32_t p1, const int32_t *label, int32_t *srcvert,
-                                 int32_t *srclab, Shared *sh) {
-    for (int64_t j0 = p0 + blockIdx.x * (int64_t)blockDim.x; j0 < p1; j0 += (int64_t)gridDim.x * blockDim.x) {
-        int64_t j = j0 + threadIdx.x;
-        int32_t v = -1, l = -1;
-        if (j < p1) {
-            v = (int32_t)perm_apply(P, (uint32_t)j);
-            l = label[v];
+// [p0, p1) (Algorithm 1: F = P_i intersect V').  Reserves output slots like
+// k_select_scan, once per kScanPer x 256 positions.
+__global__ __launch_bounds__(kBlock) void k_select_sources(Perm P, uint32_t p0, uint32_t p1, const int32_t *label,
+                                                           int32_t *srcvert, int32_t *srclab, Shared *sh) {
+    __shared__ uint32_t part[kWavesPerBlock];
+    __shared__ uint32_t base_s;
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    const int64_t tile = (int64_t)kBlock * kScanPer;
+    for (int64_t t0 = (int64_t)p0 + (int64_t)blockIdx.x * tile; t0 < (int64_t)p1; t0 += (int64_t)gridDim.x * tile) {
+        int32_t vs[kScanPer], lab[kScanPer];
+        uint32_t act = 0;
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            const int64_t j = t0 + (int64_t)r * kBlock + threadIdx.x;
+            vs[r] = -1;
+            lab[r] = -1;
+            if (j < (int64_t)p1) {
+                vs[r] = (int32_t)perm_apply(P, (uint32_t)j);
+                lab[r] = label[vs[r]];
+            }
+            act |= (lab[r] >= 0 ? 1u : 0u) << r;
         }
-        bool act = l >= 0;
-        uint64_t m = ballot(act);
-        const uint32_t base = block_reserve(&sh->k, (uint32_t)popc64(m));
-        if (act) {
-            uint32_t idx = base + rank_below(m);
-            srcvert[idx] = v;
-            srclab[idx] = l;
+        const int cnt = __popc(act);
+        const int incl = wave_incl_scan(cnt);
+        if (lane == kWave - 1) part[wv] = (uint32_t)incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tsum = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) tsum += part[w];
+            base_s = tsum ? atomicAdd(&sh->k, tsum) : 0u;
+        }
+        __syncthreads();
+        uint32_t pos = base_s + (uint32_t)(incl - cnt);
+        for (int w = 0; w < wv; w++) pos += part[w];
+        __syncthreads();  // part/base_s are rewritten next iteration
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            if ((act >> r) & 1u) {
+                srcvert[pos] = vs[r];
+                srclab[pos] = lab[r];
+                pos++;
+            }
         }
     }
 }

@@ -1059,13 +1059,15 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         if ((p1 - pos) * 16 > (uint64_t)n) {
             const bool build = !invp_built;
             if (build) ensure(c, c->invp, (uint64_t)n);
-            hipLaunchKernelGGL(k_select_scan, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, P,
+            hipLaunchKernelGGL(k_select_scan, dim3(grid_for(c, ((uint64_t)n + kScanPer - 1) / kScanPer)), dim3(kBlock),
+                               0, c->stream, P,
                                (uint32_t)pos, (uint32_t)p1, n, c->label.p, c->srcvert.p, c->srclab.p, sh, c->invp.p,
                                build);
             LAUNCHCHK("k_select_scan");
             invp_built = true;
         } else {
-            hipLaunchKernelGGL(k_select_sources, dim3(grid_for(c, p1 - pos)), dim3(kBlock), 0, c->stream, P,
+            hipLaunchKernelGGL(k_select_sources, dim3(grid_for(c, (p1 - pos + kScanPer - 1) / kScanPer)), dim3(kBlock),
+                               0, c->stream, P,
                                (uint32_t)pos, (uint32_t)p1, c->label.p, c->srcvert.p, c->srclab.p, sh);
             LAUNCHCHK("k_select_sources");
         }
