@@ -54,7 +54,9 @@ constexpr int kTimedMax = 4 * kMaxSlots;  // timed launches between host checks
 constexpr int kPhases = 5;      // trim, first, multi, resize, label
 constexpr uint32_t kProbeLimit = 128;
 constexpr uint64_t kCheapPairs = 4;  // reach pairs per source of a batch that counts as cheap
-constexpr uint64_t kDenseLabelDiv = 8;  // relabel per vertex once a batch has n / 8 pairs
+constexpr uint64_t kDenseLabelDiv = 8;
+constexpr int64_t kShortRounds = 4;      // a batch of at most this many rounds per direction is short ...
+constexpr double kShortGrowth = 64.0;    // ... and the next one grows by this factor  // relabel per vertex once a batch has n / 8 pairs
 
 }  // namespace
 
@@ -1038,7 +1040,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     // check); it is only used as an upper bound.
     uint64_t pos = j1 < (uint32_t)n ? (uint64_t)j1 + 1 : (uint64_t)n;
     double bsize = 1.0, prev_bsize = 1.0;
-    bool fast_next = false;
+    bool fast_next = false, short_next = false;
     const uint64_t lanes_all = (uint64_t)c->expand_grid[kMulti][0] * kBlock;
     int32_t epoch = 1;
     int32_t stamp_ep = c->stamp_next;  // owner-election stamp of the current batch
@@ -1048,8 +1050,12 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     while (active > 0 && pos < (uint64_t)n) {
         // Batches grow by beta (Algorithm 1), or by beta_fast after a batch
         // whose frontiers never filled the GPU's lanes: its rounds were
-        // latency bound, so a larger batch costs few extra rounds' time.
-        bsize *= (o.beta_fast > o.beta && fast_next) ? (double)o.beta_fast : (double)o.beta;
+        // latency bound, so a larger batch costs few extra rounds' time.  A
+        // batch whose searches ended within a few rounds and whose sources
+        // reached few vertices each cost little more than its fixed launches
+        // and checks, so the next one grows by kShortGrowth.
+        const double g_fast = short_next ? std::max((double)o.beta_fast, kShortGrowth) : (double)o.beta_fast;
+        bsize *= (g_fast > o.beta && fast_next) ? g_fast : (double)o.beta;
         const uint64_t sz = std::max<uint64_t>((uint64_t)std::ceil(bsize - 1e-9), 1);
         const uint64_t p1 = std::min<uint64_t>((uint64_t)n, pos + sz);
         const uint64_t kmax = std::min<uint64_t>(p1 - pos, (uint64_t)active);
@@ -1148,6 +1154,8 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         // batch may grow faster
         fast_next = DP.peak_fdeg < lanes_all / 16 ||
                     (DP.peak_fdeg < lanes_all && k > 0 && (a_out + a_in) < (uint64_t)kCheapPairs * 2 * k);
+        short_next = o.beta_fast > o.beta && std::max(L[0].rounds, L[1].rounds) <= kShortRounds &&
+                     (a_out + a_in) < (uint64_t)kCheapPairs * 2 * std::max<uint64_t>(k, 1);
         active = (int64_t)n - trimmed - count_sum(c, &CountLine::fin);
         if (k == 0) continue;  // nothing was claimed; the tables are still clean
         if (st) {
