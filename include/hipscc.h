@@ -113,8 +113,11 @@ typedef struct {
  *                its sources reached fewer than 4 vertices each (per
  *                direction) and its frontiers never exceeded the lanes.  Its
  *                rounds were latency bound, so a larger batch costs little.
- *                Any growth factor above 1 keeps Algorithm 1 correct.
- *                Default 8; <= beta turns it off.
+ *                After a batch that was also short (at most 4 rounds per
+ *                direction) and cheap in pairs (fewer than 4 reached vertices
+ *                per source and direction), the next batch grows by
+ *                max(beta_fast, 64).  Any growth factor above 1 keeps
+ *                Algorithm 1 correct.  Default 8; <= beta turns both off.
  *   vgc_fill     local search runs in rounds whose frontier has fewer arcs
  *                (entries x average degree) than vgc_fill x the lanes of the
  *                expand grid; a frontier above that keeps the GPU busy on its
