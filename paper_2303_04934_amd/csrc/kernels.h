@@ -9,8 +9,8 @@ namespace hipscc {
 
 enum { kCtrSeeds = 0, kCtrExpanded, kCtrArcs, kCtrAttempts, kCtrClaims, kCtrInserts, kNumCtr };
 constexpr int kCtrStripes = 32;
-// counter kinds: expand single-source, expand multi-source, pull, edge-parallel
-// Counter kinds: the work of each frontier kernel.
+// Counter kinds: the work of each frontier kernel (expand single-source,
+// expand multi-source, pull, edge-parallel single- and multi-source).
 enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavySingle = 3, kKindHeavyMulti = 4, kNumKinds = 5 };
 
 // Round control of one search lane (one direction of a search), in device
@@ -462,7 +462,6 @@ __global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_
     }
 }
 
-// Multi-source seed: claim (s_j, j) and put it in the frontier.
 // Multi-source seed of one or two lanes (blockIdx.y = lane): claim (s_j, j)
 // in the lane's reach table and put it in its frontier.
 struct SeedArgs {

@@ -543,9 +543,10 @@ void launch_dense(scc_ctx *c, Lane &L) {
     L.par ^= 1;
 }
 
-// A multi-source lane whose reach table overflowed restarts on a table twice
-// as large (Section 4.5 resizes once an insertion probes too often; the table
-// cannot grow while claims are in flight).
+// A multi-source lane whose reach table or frontier buffers overflowed
+// restarts on a table twice as large, with buffers to match (Section 4.5
+// resizes once an insertion probes too often; the table cannot grow while
+// claims are in flight).
 void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
     auto t0 = std::chrono::steady_clock::now();
     uint64_t &ts = *L.tslots;
