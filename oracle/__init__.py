@@ -11,8 +11,14 @@ Functions (plain definitions, see ``oracle.c`` for the citations):
 * :func:`reach_pairs` -- per-source BFS reach restricted to label-equal arcs;
 * :func:`check_partition` -- certificate (mutual reachability inside every
   class, acyclic class graph, label = class minimum);
-* :func:`hashbag_model` -- the hash bag's ExtractAll contract (Section 3.3):
-  the extracted multiset equals the multiset inserted since the last extract;
+* :func:`bfs_depths` -- per-source BFS depth of the same restricted reach
+  (the number of frontier rounds of Algorithm 2 is this depth plus one);
+* :func:`hashbag_sim` -- a sequential model of the parallel hash bag
+  (Section 3.3: doubling chunks, sampled load estimate, chunk moves, linear
+  probing, ExtractAll over the used prefix), with the statistics Theorem 1
+  bounds (load of a chunk when it is left, used prefix);
+* :func:`hashbag_model` -- ExtractAll's output per round as the model
+  produces it (sorted): the multiset inserted since the last extract;
 * :func:`policy_forward` -- float32 forward pass of the round-policy MLP.
 
 The C part is compiled with gcc (``build``); the MLP forward is numpy.
@@ -49,6 +55,10 @@ def _load():
         lib.or_tarjan.argtypes = [i64, vp, vp, vp]
         lib.or_reach_pairs.argtypes = [i64, vp, vp, vp, i64, vp, vp, i64, ctypes.POINTER(i64)]
         lib.or_check_partition.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.POINTER(i64)]
+        lib.or_bfs_depths.argtypes = [i64, vp, vp, vp, i64, vp, vp]
+        lib.or_hashbag_sim.argtypes = [i64, vp, i64, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_uint64, vp, vp, vp, vp, vp, i64,
+                                       ctypes.POINTER(i64)]
         _lib = lib
     return _lib
 
@@ -101,11 +111,58 @@ def check_partition(g, labels):
     return int(rc), int(bad.value)
 
 
-def hashbag_model(inserted_batches):
-    """ExtractAll contract (Section 3.3): after any sequence of concurrent
-    Inserts, ExtractAll returns exactly the inserted multiset (no dedupe).
-    Returns the expected extract, sorted, for each batch."""
-    return [np.sort(np.asarray(b, dtype=np.int64)) for b in inserted_batches]
+def bfs_depths(n: int, off, adj, labels, sources) -> np.ndarray:
+    """Per source: the largest BFS distance of the label-restricted reach
+    (arcs (u,w) with labels[u]==labels[w]>=0), 0 if it reaches only itself."""
+    off, adj, labels, sources = _i32(off), _i32(adj), _i32(labels), _i32(sources)
+    out = np.zeros(max(len(sources), 1), np.int32)
+    rc = _load().or_bfs_depths(n, off.ctypes.data, adj.ctypes.data if len(adj) else None, labels.ctypes.data,
+                               len(sources), sources.ctypes.data if len(sources) else None, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("or_bfs_depths rejected its input: %d" % rc)
+    return out[:len(sources)]
+
+
+def hashbag_sim(batches, lam_log2: int = 10, sigma: int = 50, alpha: float = 0.5, kappa: int = 32,
+                seed: int = 1):
+    """Sequential hash bag model (Section 3.3).  ``batches``: the keys
+    inserted in each round, each round ended by ExtractAll.  Returns a dict:
+    ``extracted`` (list of int64 arrays, slot order), ``prefix`` (used prefix
+    per round), ``advances`` (rows (chunk, load, cause) for every move of the
+    current chunk; cause 0 = sigma samples, 1 = probe limit)."""
+    arrs = [np.asarray(b, dtype=np.int64).reshape(-1) for b in batches]
+    keys = np.ascontiguousarray(np.concatenate(arrs) if arrs else np.zeros(0, np.int64))
+    starts = np.zeros(len(arrs) + 1, np.int64)
+    starts[1:] = np.cumsum([len(a) for a in arrs])
+    n = int(keys.size)
+    out = np.zeros(max(n, 1), np.int64)
+    prefix = np.zeros(max(len(arrs), 1), np.int64)
+    cap = 4096
+    while True:
+        ch = np.zeros(cap, np.int32)
+        ld = np.zeros(cap, np.float64)
+        cz = np.zeros(cap, np.int32)
+        na = ctypes.c_int64(0)
+        rc = _load().or_hashbag_sim(n, keys.ctypes.data if n else None, len(arrs), starts.ctypes.data, lam_log2,
+                                    sigma, alpha, kappa, seed, out.ctypes.data if n else None, prefix.ctypes.data,
+                                    ch.ctypes.data, ld.ctypes.data, cz.ctypes.data, cap, ctypes.byref(na))
+        if rc != 0:
+            raise RuntimeError("or_hashbag_sim failed: %d" % rc)
+        if na.value <= cap:
+            break
+        cap = int(na.value)
+    k = int(na.value)
+    ext = [out[starts[q]:starts[q + 1]].copy() for q in range(len(arrs))]
+    return {"extracted": ext, "prefix": prefix[:len(arrs)].copy(),
+            "advances": [(int(ch[i]), float(ld[i]), int(cz[i])) for i in range(k)]}
+
+
+def hashbag_model(inserted_batches, **kw):
+    """ExtractAll's output for each round (sorted), as the sequential model of
+    Section 3.3 produces it: after any sequence of Inserts, ExtractAll returns
+    exactly the inserted multiset (no dedupe)."""
+    sim = hashbag_sim(inserted_batches, **kw)
+    return [np.sort(e) for e in sim["extracted"]]
 
 
 def policy_forward(weights: np.ndarray, feats: np.ndarray, n_in: int = 5, hidden: int = 32, n_out: int = 8):

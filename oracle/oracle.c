@@ -246,3 +246,168 @@ int or_check_partition(int64_t n, const int32_t *out_off, const int32_t *out_adj
     free(indeg); free(start); free(memb); free(seen); free(queue);
     return rc;
 }
+
+/* BFS depth of each source's label-restricted reach (Section 2, "Reachability
+ * Search"; Algorithm 2 runs one frontier round per BFS level).  ecc[j] = the
+ * largest distance from sources[j] to a vertex it reaches over arcs (u, w)
+ * with labels[u] == labels[w] >= 0 (0 when it reaches only itself).  Same
+ * argument rules as or_reach_pairs. */
+int or_bfs_depths(int64_t n, const int32_t *off, const int32_t *adj, const int32_t *labels, int64_t k,
+                  const int32_t *sources, int32_t *ecc) {
+    if (n < 0 || k < 0 || (k > 0 && (!sources || !ecc))) return -1;
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!dist || !seen || !queue) { free(dist); free(seen); free(queue); return -2; }
+    for (int64_t v = 0; v < n; v++) seen[v] = -1;
+    for (int64_t j = 0; j < k; j++) {
+        int32_t s = sources[j];
+        if (s < 0 || s >= n || labels[s] < 0) { free(dist); free(seen); free(queue); return -1; }
+        int64_t head = 0, tail = 0;
+        int32_t far = 0;
+        queue[tail++] = s;
+        seen[s] = (int32_t)j;
+        dist[s] = 0;
+        while (head < tail) {
+            int32_t u = queue[head++];
+            if (dist[u] > far) far = dist[u];
+            for (int64_t e = off[u]; e < off[u + 1]; e++) {
+                int32_t w = adj[e];
+                if (labels[w] != labels[u] || seen[w] == (int32_t)j) continue;
+                seen[w] = (int32_t)j;
+                dist[w] = dist[u] + 1;
+                queue[tail++] = w;
+            }
+        }
+        ecc[j] = far;
+    }
+    free(dist); free(seen); free(queue);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Sequential model of the parallel hash bag of Section 3.3 (Figure 5 and the
+ * text around it), with one inserting processor (P = 1, the sequential case
+ * of the proof of Theorem 1 in Appendix A).
+ *
+ * Layout: chunk 0 is [0, lambda), chunk i >= 1 is [lambda 2^(i-1),
+ * lambda 2^i) (the doubling tails of Figure 5: tail[0] = lambda, tail[i] =
+ * 2 tail[i-1]); the array holds chunks 0..C-1 with lambda 2^(C-1) >= (s_max +
+ * lambda) / alpha, s_max the largest round.  Insert(k): with r' the current
+ * chunk, the element is sampled with probability sigma / (alpha |chunk r'|);
+ * a sample increments sample[r'] and, once sample[r'] reaches sigma, moves r
+ * from r' to r' + 1 and inserts k again.  Otherwise k goes to a uniformly
+ * random slot of chunk r' and probes linearly (wrapping inside the chunk);
+ * more than kappa probes also move r forward and insert k again.  The last
+ * chunk never moves r.  ExtractAll lists the non-empty slots of [0,
+ * tail[r]) in index order, empties them and resets r and the samples.
+ *
+ * Randomness: SplitMix64 (Steele, Lea, Flood 2014) of a running counter
+ * seeded by `seed`, written here for this model.
+ *
+ * keys[0..n) are inserted round by round: round q holds keys
+ * [round_start[q], round_start[q+1]).  Outputs:
+ *   out[n]            the extracted keys, round after round;
+ *   prefix[q]         tail[r] when round q was extracted (the used prefix);
+ *   adv_chunk/adv_load/adv_cause[adv_cap]  one row per move of r: the chunk
+ *                     left, its load (occupied / size) at that moment, and
+ *                     the cause (0 sample count reached sigma, 1 probe limit);
+ *   *n_adv            the number of moves (rows beyond adv_cap dropped).
+ * Returns 0, -1 bad argument, -2 out of memory, -4 the last chunk filled. */
+static uint64_t bag_sm64(uint64_t *state) {
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int or_hashbag_sim(int64_t n, const int64_t *keys, int64_t rounds, const int64_t *round_start, int32_t lam_log2,
+                   int32_t sigma, double alpha, int32_t kappa, uint64_t seed, int64_t *out, int64_t *prefix,
+                   int32_t *adv_chunk, double *adv_load, int32_t *adv_cause, int64_t adv_cap, int64_t *n_adv) {
+    if (n < 0 || rounds < 0 || lam_log2 < 0 || lam_log2 > 40 || sigma < 1 || !(alpha > 0.0 && alpha < 1.0) ||
+        kappa < 0 || !n_adv || (rounds > 0 && (!round_start || !prefix)) || (n > 0 && (!keys || !out)))
+        return -1;
+    *n_adv = 0;
+    int64_t smax = 0;
+    for (int64_t q = 0; q < rounds; q++) {
+        int64_t s = round_start[q + 1] - round_start[q];
+        if (s < 0 || round_start[q + 1] > n) return -1;
+        if (s > smax) smax = s;
+    }
+    const uint64_t lam = 1ull << lam_log2;
+    int nchunks = 1;
+    while ((double)(lam << (nchunks - 1)) < ((double)smax + (double)lam) / alpha) nchunks++;
+    const uint64_t cap = lam << (nchunks - 1);
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * cap);
+    uint8_t *used = (uint8_t *)calloc(cap, 1);
+    int64_t *fill = (int64_t *)calloc((size_t)nchunks, sizeof(int64_t));
+    int64_t *sample = (int64_t *)calloc((size_t)nchunks, sizeof(int64_t));
+    if (!slot || !used || !fill || !sample) { free(slot); free(used); free(fill); free(sample); return -2; }
+    uint64_t rng = seed;
+    int64_t w = 0;
+    int rc = 0;
+    for (int64_t q = 0; q < rounds && rc == 0; q++) {
+        int r = 0;
+        for (int64_t i = round_start[q]; i < round_start[q + 1] && rc == 0; i++) {
+            const int64_t key = keys[i];
+            for (;;) {
+                const int rr = r;
+                const uint64_t lo = rr == 0 ? 0 : (lam << (rr - 1)), hi = lam << rr;
+                const uint64_t size = hi - lo;
+                const int last = rr == nchunks - 1;
+                int moved = 0;
+                if (!last) {
+                    /* sampled with probability sigma / (alpha * size) */
+                    const double u = (double)(bag_sm64(&rng) >> 11) * (1.0 / 9007199254740992.0);
+                    if (u * alpha * (double)size < (double)sigma) {
+                        if (++sample[rr] >= sigma) {
+                            if (*n_adv < adv_cap) {
+                                adv_chunk[*n_adv] = rr;
+                                adv_load[*n_adv] = (double)fill[rr] / (double)size;
+                                adv_cause[*n_adv] = 0;
+                            }
+                            (*n_adv)++;
+                            r = rr + 1;
+                            moved = 1;
+                        }
+                    }
+                }
+                if (moved) continue;
+                uint64_t pos = lo + bag_sm64(&rng) % size;
+                int64_t probes = 0;
+                while (used[pos]) {
+                    pos = pos + 1 == hi ? lo : pos + 1;
+                    probes++;
+                    if (!last && probes > kappa) break;
+                    if (last && (uint64_t)probes >= size) break;
+                }
+                if (used[pos]) {
+                    if (last) { rc = -4; break; }
+                    if (*n_adv < adv_cap) {
+                        adv_chunk[*n_adv] = rr;
+                        adv_load[*n_adv] = (double)fill[rr] / (double)size;
+                        adv_cause[*n_adv] = 1;
+                    }
+                    (*n_adv)++;
+                    r = rr + 1;
+                    continue;
+                }
+                used[pos] = 1;
+                slot[pos] = key;
+                fill[rr]++;
+                break;
+            }
+        }
+        /* ExtractAll: the used prefix [0, tail[r]) in index order, cleared */
+        const uint64_t tail = lam << r;
+        prefix[q] = (int64_t)tail;
+        for (uint64_t p = 0; p < tail; p++) {
+            if (!used[p]) continue;
+            out[w++] = slot[p];
+            used[p] = 0;
+        }
+        for (int c = 0; c < nchunks; c++) { fill[c] = 0; sample[c] = 0; }
+    }
+    free(slot); free(used); free(fill); free(sample);
+    return rc;
+}

@@ -225,3 +225,201 @@ def test_hashbag_model_is_multiset_identity():
     batches = [[5, 1, 5, 3], [], [2]]
     out = oracle.hashbag_model(batches)
     assert [list(b) for b in out] == [[1, 3, 5, 5], [], [2]]
+
+
+# ---------------------------------------------------------------- policy ----
+# Closed forms for the MLP forward, built from the documented blob layout
+# [W1 (32 x 5), b1 (32), W2 (32 x 32), b2 (32), W3 (8 x 32), b3 (8)], row-major
+# out x in.  None of them recomputes the forward with matrix products: each
+# predicts the output from the layout alone, so a transposed block, a wrong
+# offset, a dropped bias or ReLU fails one of them.
+N_IN, HID, N_OUT = 5, 32, 8
+OFF_W1 = 0
+OFF_B1 = OFF_W1 + HID * N_IN
+OFF_W2 = OFF_B1 + HID
+OFF_B2 = OFF_W2 + HID * HID
+OFF_W3 = OFF_B2 + HID
+OFF_B3 = OFF_W3 + N_OUT * HID
+N_W = OFF_B3 + N_OUT
+
+
+def _identity_net():
+    """h1 = 1 for every hidden unit (W1 = 0, b1 = 1), h2 = h1 (W2 = I),
+    y[o] = h2[o] (W3 row o picks hidden unit o), b3 = 0: y = 1 everywhere."""
+    w = np.zeros(N_W, np.float32)
+    w[OFF_B1:OFF_B1 + HID] = 1.0
+    for i in range(HID):
+        w[OFF_W2 + i * HID + i] = 1.0
+    for o in range(N_OUT):
+        w[OFF_W3 + o * HID + o] = 1.0
+    return w
+
+
+def test_policy_forward_one_hot_copies_inputs():
+    # W1 row i (i < 5) = e_i, W2 = I, W3 row o = e_o: y[o] = relu(x[o]) for
+    # o < 5 and y[o] = b3[o] for the other outputs
+    w = np.zeros(N_W, np.float32)
+    for i in range(N_IN):
+        w[OFF_W1 + i * N_IN + i] = 1.0
+    for i in range(HID):
+        w[OFF_W2 + i * HID + i] = 1.0
+    for o in range(N_OUT):
+        w[OFF_W3 + o * HID + o] = 1.0
+    w[OFF_B3:OFF_B3 + N_OUT] = [0, 0, 0, 0, 0, 7.5, -2.25, 0.125]
+    x = np.array([[1.5, -2.0, 3.25, 0.0, 9.0], [-1, -1, -1, -1, -1]], np.float32)
+    y = oracle.policy_forward(w, x)
+    assert np.array_equal(y[0], np.array([1.5, 0.0, 3.25, 0.0, 9.0, 7.5, -2.25, 0.125], np.float32))
+    assert np.array_equal(y[1], np.array([0, 0, 0, 0, 0, 7.5, -2.25, 0.125], np.float32))
+
+
+def test_policy_forward_dead_relus_give_b3():
+    # every pre-activation of both hidden layers negative: the output is b3 exactly
+    rng = np.random.default_rng(11)
+    w = (rng.standard_normal(N_W) * 0.01).astype(np.float32)
+    w[OFF_B1:OFF_B1 + HID] = -100.0
+    w[OFF_B2:OFF_B2 + HID] = -1.0
+    x = rng.uniform(-3, 3, size=(16, N_IN)).astype(np.float32)
+    y = oracle.policy_forward(w, x)
+    assert np.array_equal(y, np.tile(w[OFF_B3:OFF_B3 + N_OUT], (16, 1)))
+
+
+def _perturbation_prediction(f, x, delta):
+    """Output change of _identity_net() when blob entry f grows by delta, from
+    the layout: (block, row, column) of f decides which unit moves."""
+    d = np.zeros(N_OUT)
+    if f < OFF_B1:                       # W1[i, j]: h1[i] += delta * x[j]
+        i, j = divmod(f - OFF_W1, N_IN)
+        if i < N_OUT:
+            d[i] = delta * x[j]
+    elif f < OFF_W2:                     # b1[i]
+        i = f - OFF_B1
+        if i < N_OUT:
+            d[i] = delta
+    elif f < OFF_B2:                     # W2[i, j]: h2[i] += delta * h1[j] = delta
+        i, _ = divmod(f - OFF_W2, HID)
+        if i < N_OUT:
+            d[i] = delta
+    elif f < OFF_W3:                     # b2[i]
+        i = f - OFF_B2
+        if i < N_OUT:
+            d[i] = delta
+    elif f < OFF_B3:                     # W3[o, p]: y[o] += delta * h2[p] = delta
+        o, _ = divmod(f - OFF_W3, HID)
+        d[o] = delta
+    else:                                # b3[o]
+        d[f - OFF_B3] = delta
+    return d
+
+
+def _check_every_blob_offset(forward):
+    x = np.array([1.0, 2.0, 3.0, 4.0, 5.0], np.float32)
+    base = _identity_net()
+    y0 = forward(base, x[None])[0].astype(np.float64)
+    assert np.array_equal(y0, np.ones(N_OUT))
+    bad = []
+    for f in range(N_W):
+        w = base.copy()
+        w[f] += np.float32(0.5)
+        dy = forward(w, x[None])[0].astype(np.float64) - y0
+        if not np.allclose(dy, _perturbation_prediction(f, x, 0.5), rtol=0, atol=1e-6):
+            bad.append(f)
+    return bad
+
+
+def test_policy_forward_blob_layout_every_offset():
+    assert _check_every_blob_offset(oracle.policy_forward) == []
+
+
+def test_policy_layout_pin_catches_transposed_w1():
+    # the same check fails for a forward that reads W1 as (in x out)
+    def transposed_w1(w, x):
+        w2 = w.copy()
+        w2[OFF_W1:OFF_B1] = w[OFF_W1:OFF_B1].reshape(N_IN, HID).T.reshape(-1)
+        return oracle.policy_forward(w2, x)
+    assert len(_check_every_blob_offset(transposed_w1)) > 0
+
+
+# ------------------------------------------------------------ BFS depths ----
+def test_bfs_depths_closed_forms():
+    n = 300
+    path = csr_of(n, [(i, i + 1) for i in range(n - 1)])
+    lab = np.zeros(n, np.int32)
+    assert list(oracle.bfs_depths(n, path.out_off, path.out_adj, lab, [0, 100, n - 1])) == [n - 1, n - 1 - 100, 0]
+    cyc = csr_of(n, [(i, (i + 1) % n) for i in range(n)])
+    assert list(oracle.bfs_depths(n, cyc.out_off, cyc.out_adj, lab, [0, 5])) == [n - 1, n - 1]
+    # right/down grid from the top-left corner: the Manhattan distance to the far corner
+    r, c = 17, 23
+    arcs = [(i * c + j, i * c + j + 1) for i in range(r) for j in range(c - 1)]
+    arcs += [(i * c + j, (i + 1) * c + j) for i in range(r - 1) for j in range(c)]
+    g = csr_of(r * c, arcs)
+    assert oracle.bfs_depths(g.n, g.out_off, g.out_adj, np.zeros(g.n, np.int32), [0])[0] == r + c - 2
+    # a label boundary cuts the path
+    lab2 = np.zeros(n, np.int32)
+    lab2[150:] = 1
+    assert list(oracle.bfs_depths(n, path.out_off, path.out_adj, lab2, [0, 150])) == [149, n - 151]
+    with pytest.raises(ValueError):
+        lab3 = lab.copy()
+        lab3[7] = -1
+        oracle.bfs_depths(n, path.out_off, path.out_adj, lab3, [7])
+
+
+def test_bfs_depths_vs_scipy_shortest_paths():
+    from scipy.sparse.csgraph import shortest_path
+    rng = np.random.default_rng(12)
+    for t in range(40):
+        g = graphgen.random_digraph(int(rng.integers(2, 400)), float(rng.choice([0.8, 1.5, 3.0])), seed=8100 + t)
+        labels = rng.integers(-1, 2, size=g.n).astype(np.int32)
+        cand = np.nonzero(labels >= 0)[0]
+        if len(cand) == 0:
+            continue
+        src = rng.permutation(cand)[:5].astype(np.int32)
+        u = np.repeat(np.arange(g.n), np.diff(g.out_off))
+        keep = (labels[u] == labels[g.out_adj]) & (labels[u] >= 0)
+        A = sp.csr_matrix((np.ones(int(keep.sum())), (u[keep], g.out_adj[keep])), shape=(g.n, g.n))
+        D = shortest_path(A, method="D", directed=True, unweighted=True, indices=src)
+        want = [int(np.max(D[j][np.isfinite(D[j])])) for j in range(len(src))]
+        assert list(oracle.bfs_depths(g.n, g.out_off, g.out_adj, labels, src)) == want
+
+
+# -------------------------------------------------------------- hash bag ----
+def test_hashbag_model_returns_the_inserted_multiset():
+    from collections import Counter
+    rng = np.random.default_rng(4)
+    batches = [[5, 1, 5, 3], [], [2], rng.integers(0, 50, size=20000), rng.integers(0, 1 << 40, size=70000)]
+    sim = oracle.hashbag_sim(batches, lam_log2=8)
+    for b, e in zip(batches, sim["extracted"]):
+        assert Counter(np.asarray(b, np.int64).tolist()) == Counter(e.tolist())
+    assert [list(x) for x in oracle.hashbag_model(batches[:3])] == [[1, 3, 5, 5], [], [2]]
+
+
+@pytest.mark.parametrize("s", [3000, 40000, 250000])
+def test_hashbag_model_theorem1_load_and_prefix(s):
+    # Theorem 1 / Appendix A with alpha = 1/2: a chunk is left at load in
+    # [1/4, 3/4] w.h.p., and s elements sit in the first O(s + lambda) slots
+    lam = 1 << 10
+    loads, moves = [], 0
+    for seed in range(24):
+        keys = np.arange(s, dtype=np.int64) * 7919 + seed
+        sim = oracle.hashbag_sim([keys], lam_log2=10, sigma=50, alpha=0.5, kappa=32, seed=seed + 1)
+        for chunk, load, cause in sim["advances"]:
+            moves += 1
+            if cause == 0:
+                loads.append(load)
+        assert sim["prefix"][0] <= 8 * (s + lam)
+        assert sim["prefix"][0] >= s
+    assert loads and all(0.25 <= x <= 0.75 for x in loads), (min(loads), max(loads))
+    # the sample count, not the probe limit, moves the chunk almost always
+    assert len(loads) >= 0.9 * moves
+
+
+def test_hashbag_model_small_round_stays_in_first_chunk():
+    sim = oracle.hashbag_sim([np.arange(64)] * 5, lam_log2=10)
+    assert sim["advances"] == [] and list(sim["prefix"]) == [1024] * 5
+
+
+def test_hashbag_load_pin_catches_a_wrong_sample_rate():
+    # a model whose sample rate ignores alpha (rate sigma / size, i.e. alpha
+    # near 1) leaves chunks nearly full: the Theorem 1 interval rejects it
+    sim = oracle.hashbag_sim([np.arange(200000)], lam_log2=10, sigma=50, alpha=0.97, kappa=1 << 20, seed=3)
+    loads = [ld for _, ld, cause in sim["advances"] if cause == 0]
+    assert loads and max(loads) > 0.75
