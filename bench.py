@@ -1,15 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: SCC labels of a synthetic digraph on one MI355X.
+"""Benchmark: SCC labels of synthetic digraphs on one MI355X.
 
-One step = one full scc_labels call (trim, first-SCC searches, every
-multi-source batch, relabels, canonical labels) on a graph already resident
-in HBM.  Prints one JSON line.  ``value`` = input arcs / wall time of a step
-(edges/s).  ``roofline`` covers the dominant kernel (the frontier-expansion
-kernel of the mode that took longest), from its algorithmic bytes and its
-HIP-event time measured over the timed steps.  ``cpu_baseline`` times the
-sequential Tarjan oracle on the same graph on one host core.
+Default workload: the batched configuration, 4096 independent digraphs
+(vertex counts log-uniform in [1e3, 1e6], family uniform among the 2-D torus,
+R-MAT edge factor 8 and 3-D k-NN k=5; 590M vertices, 2.9G arcs), resident in
+HBM, labelled by scc_labels_batched with the schedule the autotuner picked
+on half of the graphs.  One step = one scc_labels_batched call over the whole
+batch (trim, first-SCC searches, every multi-source batch, relabels,
+canonical labels of every graph).  Beside it, outside the timed region: the
+same batch with the default schedule, with the default schedule plus the
+learned policy, and as a loop of one plain scc_labels call per graph.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload rmat_s24_ef16]
+Single-graph workloads (--workload): one step = one scc_labels call.
+
+Prints one JSON line.  ``value`` = input arcs / wall time of a step
+(edges/s).  ``roofline`` covers the dominant frontier kernel, from its
+algorithmic bytes and its HIP-event time over the timed steps.
+``cpu_baseline`` times the Tarjan oracle on the host cores (batched: a thread
+pool over the independent graphs).
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload batched4096]
 """
 import argparse
 import hashlib
@@ -31,15 +41,27 @@ WORKLOADS = {
                       "in the unit cube, ties to the lower id"),
     "grid10000_p0.5": (3, "2-D grid 10000x10000 (no wrap), each neighbour arc kept with p=0.5"),
     "batched4096": (4, "4096 graphs, vertex counts log-uniform in [1e3, 10^hi] (hi = --batch-hi, default 6), "
-                       "family uniform in {torus p=0.5, R-MAT edge factor 8, 3-D k-NN k=5}, run as one disjoint "
-                       "union with an autotuned schedule"),
+                       "family uniform in {torus p=0.5, R-MAT edge factor 8, 3-D k-NN k=5}, run as disjoint "
+                       "unions with an autotuned schedule"),
+    "sqr_10000": (5, "the paper's SQR lattice: 10000x10000 torus, each endpoint orients each of its edges at "
+                     "random, duplicates removed (1.5 arcs per edge)"),
+    "rec_1000x10000": (6, "the paper's REC lattice: 1000x10000 torus, each endpoint orients each of its edges at "
+                          "random, duplicates removed (1.5 arcs per edge)"),
+    "sqr2_10000": (7, "the paper's SQR' lattice: 10000x10000 torus, each arc of each edge kept with p=0.3"),
+    "rec2_1000x10000": (8, "the paper's REC' lattice: 1000x10000 torus, each arc of each edge kept with p=0.3"),
 }
+DEFAULT_WORKLOAD = "batched4096"
 BATCH_G, BATCH_LO, BATCH_SEED = 4096, 3.0, 1004
 # the frontier kernels timed with options.timing, as rocprofv3 names them
 KERNEL_NAMES = ["hipscc::k_expand<0, 1>", "hipscc::k_expand<1, 1>", "hipscc::k_pull", "hipscc::k_expand_heavy<0>",
                 "hipscc::k_expand_heavy<1>", "hipscc::k_bag_extract"]
 KERNEL_SHORT = ["k_expand0", "k_expand1", "k_pull", "k_heavy0", "k_heavy1", "k_extract"]
 NK = len(KERNEL_NAMES)
+CPU_POOL = 16  # host threads for the multicore oracle (the CPU share of one GPU)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def source_hash():
@@ -51,9 +73,9 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, mode):
+def load_traffic(workload, kernel):
     """Counter-measured HBM bytes per launch from profiles/, if taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (KERNEL_SHORT[mode], workload))
+    p = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (KERNEL_SHORT[kernel], workload))
     if not os.path.exists(p):
         return None
     try:
@@ -65,29 +87,101 @@ def load_traffic(workload, mode):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(g, runs):
+def host_info():
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline_single(g, target_s=20.0, max_runs=5):
+    """Tarjan oracle on one core: 1 warm-up, then up to max_runs timed runs
+    while their sum stays near target_s (mean and minimum reported)."""
     import oracle
+    t0 = time.perf_counter()
+    lab = oracle.scc_graph(g)
+    warm = time.perf_counter() - t0
     ts = []
-    lab = None
-    for _ in range(runs):
+    while len(ts) < max_runs and (not ts or sum(ts) + ts[-1] <= target_s):
         t0 = time.perf_counter()
-        lab = oracle.scc_graph(g)
+        oracle.scc_graph(g)
         ts.append(time.perf_counter() - t0)
     t = sum(ts) / len(ts)
+    info = host_info()
     return lab, {"value": g.m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
-                 "sample": "whole graph, %d run(s) of the sequential Tarjan oracle, mean %.3f s" % (runs, t)}
+                 "sample": "whole graph; sequential Tarjan oracle, 1 warm-up (%.2f s) then %d timed run(s): "
+                           "mean %.3f s, min %.3f s" % (warm, len(ts), t, min(ts)),
+                 "host": info}
+
+
+def cpu_baseline_batched(n_of, oo, oa, vb, ab, runs=3):
+    """Tarjan oracle over the independent graphs of a batch, a thread pool of
+    CPU_POOL host threads (the oracle runs in C and releases the GIL).
+    1 warm-up (its labels are the parity reference), then `runs` timed runs."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    G = len(vb) - 1
+    threads = max(1, min(CPU_POOL, os.cpu_count() or 1))
+    order = sorted(range(G), key=lambda g: -int(ab[g + 1] - ab[g]))  # largest first
+
+    def one(g):
+        lo = int(vb[g]) + g
+        n = int(vb[g + 1] - vb[g])
+        return g, oracle.scc_labels(n, oo[lo:lo + n + 1], oa[int(ab[g]):int(ab[g + 1])])
+
+    def sweep():
+        with ThreadPoolExecutor(threads) as ex:
+            return dict(ex.map(one, order))
+
+    t0 = time.perf_counter()
+    labels = sweep()
+    warm = time.perf_counter() - t0
+    log("oracle warm-up over %d graphs on %d threads: %.1f s" % (G, threads, warm))
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        sweep()
+        ts.append(time.perf_counter() - t0)
+    t = sum(ts) / len(ts)
+    m = int(ab[-1])
+    return labels, {"value": m / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
+                    "sample": "every graph of the batch; sequential Tarjan oracle per graph on a pool of %d host "
+                              "threads, 1 warm-up (%.1f s) then %d timed runs: mean %.2f s, min %.2f s"
+                              % (threads, warm, runs, t, min(ts)),
+                    "host": host_info()}
+
+
+def roofline(ms_k, launches_k, bytes_k, dom, workload):
+    if launches_k[dom] <= 0 or ms_k[dom] <= 0:
+        return None
+    per_launch_ms = ms_k[dom] / launches_k[dom]
+    per_launch_bytes = bytes_k[dom] / launches_k[dom]
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(workload, dom),
+            "avg_launch_ms": per_launch_ms, "alg_bytes_per_launch": per_launch_bytes}
+
+
+def load_policy(scc):
+    import numpy as np
+    scc.policy_load(np.load(os.path.join(ROOT, "paper_2303_04934_amd", "policy_weights.npy")))
 
 
 def run_batched(args, desc):
-    """The batched workload: many graphs resident in HBM, one scc_labels_batched
-    call per step with the schedule the autotuner picked; the same batch run
-    with the default schedule and as a loop of per-graph scc_labels calls is
-    timed once for comparison (outside the timed region)."""
+    """The batched workload: many graphs resident in HBM, one
+    scc_labels_batched call per step with the autotuned schedule."""
     import numpy as np
     import torch
 
     import graphgen
-    import oracle
     import paper_2303_04934_amd as scc
     from paper_2303_04934_amd import autotune
 
@@ -96,20 +190,21 @@ def run_batched(args, desc):
     graphs = []
     for i in range(0, BATCH_G, 256):  # generated in slices, with progress lines
         graphs += graphgen.batched_slice(BATCH_G, BATCH_SEED, BATCH_LO, args.batch_hi, i, min(BATCH_G, i + 256))
-        print("[bench] generated %d/%d graphs (%.0f s)" % (len(graphs), BATCH_G, time.perf_counter() - t0),
-              file=sys.stderr, flush=True)
+        log("generated %d/%d graphs (%.0f s)" % (len(graphs), BATCH_G, time.perf_counter() - t0))
     assert len(graphs) == len(spec)
     vb, ab, oo, oa, io, ia = graphgen.concat(graphs)
-    print("[bench] generated %d graphs, n=%d m=%d in %.1f s" % (len(graphs), vb[-1], ab[-1], time.perf_counter() - t0),
-          file=sys.stderr, flush=True)
+    del graphs  # the oracle reads per-graph views of the concatenated arrays
+    log("generated %d graphs, n=%d m=%d in %.1f s" % (BATCH_G, vb[-1], ab[-1], time.perf_counter() - t0))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).to("cuda:0")
     arrs = (dev(oo), dev(oa), dev(io), dev(ia))
+    del io, ia
+    load_policy(scc)
     base = scc.default_options(validate=0)
     t0 = time.perf_counter()
     opts, tuned = autotune.tune(vb, ab, *arrs, base_options=base)
-    print("[bench] autotune picked tau=%d beta=%.1f beta_fast=%.0f in %.1f s" % (opts.tau, opts.beta, opts.beta_fast,
-                                                                           time.perf_counter() - t0),
-          file=sys.stderr, flush=True)
+    log("autotune picked tau=%d beta=%.1f beta_fast=%.0f policy=%d in %.1f s (held out: %.1f ms tuned vs %.1f "
+        "default)" % (opts.tau, opts.beta, opts.beta_fast, opts.policy, time.perf_counter() - t0,
+                      tuned.get("held_out_tuned_ms", 0), tuned.get("held_out_default_ms", 0)))
     # warm-up; its last call times every frontier kernel to pick the dominant one
     for i in range(max(args.warmup, 1)):
         opts.timing = (1 << NK) - 1 if i == max(args.warmup, 1) - 1 else 0
@@ -126,62 +221,140 @@ def run_batched(args, desc):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     got = out.cpu().numpy()
-    print("[bench] timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3), file=sys.stderr, flush=True)
-    # comparisons (untimed region): default schedule, and one scc_labels call per graph
-    base.timing = opts.timing  # the same event overhead as the timed steps
+    log("timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3))
+
+    # comparisons (untimed region), with the same event overhead as the timed steps
+    def once(o):
+        o.timing = opts.timing
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = scc.scc_labels_batched(vb, ab, *arrs, options=o)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) * 1e3, r
+    default_ms, r_def = once(scc.default_options(validate=0))
+    learned_ms, r_lrn = once(scc.default_options(validate=0, policy=1))
+    same_def = bool(torch.equal(r_def, out))
+    same_lrn = bool(torch.equal(r_lrn, out))
+    del r_def, r_lrn
+    log("one scc_labels call per graph ...")
+    plain = scc.default_options(validate=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    scc.scc_labels_batched(vb, ab, *arrs, options=base)
-    base.timing = 0
-    torch.cuda.synchronize()
-    default_ms = (time.perf_counter() - t0) * 1e3
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loop_out = []
-    print("[bench] one scc_labels call per graph ...", file=sys.stderr, flush=True)
-    for g in range(len(graphs)):
+    loop_same = True
+    for g in range(BATCH_G):
         n, lo = int(vb[g + 1] - vb[g]), int(vb[g]) + g
         dg = scc.DeviceGraph(n, int(ab[g + 1] - ab[g]), arrs[0][lo:lo + n + 1], arrs[1][int(ab[g]):int(ab[g + 1])],
                              arrs[2][lo:lo + n + 1], arrs[3][int(ab[g]):int(ab[g + 1])])
-        loop_out.append(scc.scc_labels(dg, base))
+        r = scc.scc_labels(dg, plain)
+        loop_same = loop_same and bool(torch.equal(r, out[int(vb[g]):int(vb[g + 1])]))
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - t0) * 1e3
-    loop_same = all(np.array_equal(loop_out[g].cpu().numpy(), got[vb[g]:vb[g + 1]]) for g in range(len(graphs)))
-    print("[bench] default schedule %.1f ms, per-graph loop %.1f ms" % (default_ms, loop_ms), file=sys.stderr,
-          flush=True)
+    log("default schedule %.1f ms, default + learned policy %.1f ms, per-graph loop %.1f ms"
+        % (default_ms, learned_ms, loop_ms))
     m = int(ab[-1])
     line = {
         "metric": METRIC, "value": m / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "batched4096", "description": desc, "graphs": len(graphs), "n": int(vb[-1]), "m": m,
+        "config": {"workload": "batched4096", "description": desc, "graphs": BATCH_G, "n": int(vb[-1]), "m": m,
                    "seed": BATCH_SEED, "size_exponents": [BATCH_LO, args.batch_hi], "tau": opts.tau,
-                   "beta": opts.beta, "beta_fast": opts.beta_fast, "schedule": "autotuned"},
-        "batched_vs_plain": {"autotuned_batched_ms": dt * 1e3, "default_batched_ms": default_ms,
-                             "per_graph_loop_ms": loop_ms, "loop_labels_identical": loop_same,
-                             "autotune": tuned},
+                   "beta": opts.beta, "beta_fast": opts.beta_fast, "policy": "learned" if opts.policy == 1 else
+                   "fixed", "schedule": "autotuned"},
+        "batched_vs_plain": {
+            "autotuned_batched_ms": dt * 1e3, "default_batched_ms": default_ms,
+            "default_batched_learned_policy_ms": learned_ms, "per_graph_loop_ms": loop_ms,
+            "speedup_vs_per_graph_loop": loop_ms / (dt * 1e3), "labels_identical": same_def and same_lrn and loop_same,
+            "autotune": tuned},
     }
-    per_launch_ms = sum(s["ms_kernel"][dom] for s in stats) / max(1, sum(s["launches_kernel"][dom] for s in stats))
-    per_launch_bytes = sum(s["bytes_kernel"][dom] for s in stats) / max(1, sum(s["launches_kernel"][dom] for s in stats))
-    if per_launch_ms > 0:
-        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-        line["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                            "avg_launch_ms": per_launch_ms, "alg_bytes_per_launch": per_launch_bytes}
+    ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
+    la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
+    by_k = [sum(s["bytes_kernel"][i] for s in stats) for i in range(NK)]
+    rf = roofline(ms_k, la_k, by_k, dom, "batched4096")
+    if rf:
+        rf["launches_per_step"] = la_k[dom] / args.steps
+        rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)
+        line["roofline"] = rf
+    last = stats[-1]
     line["stats"] = {"kernel_ms_warmup_call": {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)},
-                     "batches": stats[-1]["batches"], "rounds_first": stats[-1]["rounds_first"],
-                     "rounds_multi": stats[-1]["rounds_multi"]}
+                     "batches": last["batches"], "rounds_first": last["rounds_first"],
+                     "rounds_multi": last["rounds_multi"], "table_restarts": last["table_restarts"],
+                     "n_scc": last["n_scc"], "bytes_alg": last["bytes_alg"],
+                     "alg_GBps_whole_step": last["bytes_alg"] / dt / 1e9}
     if not args.no_cpu_baseline:
-        t0 = time.perf_counter()
-        ok = True
-        for g, gr in enumerate(graphs):
-            ok = ok and bool(np.array_equal(oracle.scc_graph(gr), got[vb[g]:vb[g + 1]]))
-            if g % 512 == 511:
-                print("[bench] oracle %d/%d graphs (%.0f s)" % (g + 1, len(graphs), time.perf_counter() - t0),
-                      file=sys.stderr, flush=True)
-        t = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
-                                "sample": "every graph of the batch, sequential Tarjan oracle, %.1f s" % t}
+        want, cb = cpu_baseline_batched(None, oo, oa, vb, ab)
+        ok = all(np.array_equal(want[g], got[vb[g]:vb[g + 1]]) for g in range(BATCH_G))
+        line["cpu_baseline"] = cb
+        line["parity"] = "bit-exact vs oracle (every graph)" if ok else "MISMATCH vs oracle"
+    print(json.dumps(line), flush=True)
+    if line.get("parity", "").startswith("MISMATCH") or not line["batched_vs_plain"]["labels_identical"]:
+        sys.exit(1)
+
+
+def run_single(args, cfg, desc):
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2303_04934_amd as scc
+
+    t0 = time.perf_counter()
+    g = graphgen.config(cfg, shrink=args.shrink)
+    log("generated %s n=%d m=%d in %.1f s" % (args.workload, g.n, g.m, time.perf_counter() - t0))
+    dg = scc.to_device(g, "cuda:0")
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    opts = scc.default_options(timing=0, validate=0, policy=args.policy)
+    if args.tau:
+        opts.tau = args.tau
+    if args.policy == 1:
+        load_policy(scc)
+    # Untimed warm-up.  Its last call times every frontier kernel to find the
+    # dominant one; the timed steps then bracket only that kernel's launches
+    # with events (each event pair costs a little, so the others run bare).
+    for i in range(max(args.warmup, 1)):
+        opts.timing = (1 << NK) - 1 if i == max(args.warmup, 1) - 1 else 0
+        _, st = scc.scc_labels(dg, opts, out=out, return_stats=True)
+    dom = max(range(NK), key=lambda i: st["ms_kernel"][i])
+    probe_ms = list(st["ms_kernel"])
+    opts.timing = 1 << dom
+    torch.cuda.synchronize()
+    log("warmup done; dominant frontier kernel %s" % KERNEL_NAMES[dom])
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = scc.scc_labels(dg, opts, return_stats=True, out=out)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    got = out.cpu().numpy()
+    log("timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3))
+    line = {
+        "metric": METRIC, "value": g.m / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": g.n, "m": g.m, "seed": 1000 + cfg,
+                   "tau": opts.tau, "policy": "learned" if args.policy == 1 else "fixed",
+                   "shrink": args.shrink},
+    }
+    ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
+    la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
+    by_k = [sum(s["bytes_kernel"][i] for s in stats) for i in range(NK)]
+    rf = roofline(ms_k, la_k, by_k, dom, args.workload)
+    if rf:
+        rf["launches_per_step"] = la_k[dom] / args.steps
+        rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)
+        line["roofline"] = rf
+    last = stats[-1]
+    line["stats"] = {k: last[k] for k in ("ms_trim", "ms_first", "ms_multi", "ms_resize", "ms_label", "batches",
+                                         "rounds_first", "rounds_multi", "dense_rounds", "trimmed", "n_scc",
+                                         "arcs_scanned", "claims", "bag_inserts", "table_restarts", "bytes_alg")}
+    line["stats"]["alg_GBps_whole_step"] = last["bytes_alg"] / dt / 1e9
+    # every frontier kernel's event time in the (untimed) warm-up call that picked the dominant one
+    line["stats"]["kernel_ms_warmup_call"] = {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)}
+    if not args.no_cpu_baseline:
+        want, cb = cpu_baseline_single(g)
+        line["cpu_baseline"] = cb
+        ok = bool(np.array_equal(got, want))
         line["parity"] = "bit-exact vs oracle" if ok else "MISMATCH vs oracle"
     print(json.dumps(line), flush=True)
     if line.get("parity", "").startswith("MISMATCH"):
@@ -193,10 +366,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat_s24_ef16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--shrink", type=int, default=0, help="reduce n by 2**shrink (exploration only)")
     ap.add_argument("--tau", type=int, default=0, help="VGC budget (0: the library default)")
-    ap.add_argument("--cpu-runs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--policy", type=int, default=0, help="0 fixed budget, 1 learned per-round policy")
     ap.add_argument("--batch-hi", type=float, default=6.0,
@@ -217,95 +389,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-
     cfg, desc = WORKLOADS[args.workload]
     if args.workload == "batched4096":
         run_batched(args, desc)
-        return
-
-    import numpy as np
-    import torch
-
-    import graphgen
-    import paper_2303_04934_amd as scc
-
-    t0 = time.perf_counter()
-    g = graphgen.config(cfg, shrink=args.shrink)
-    print("[bench] generated %s n=%d m=%d in %.1f s" % (args.workload, g.n, g.m, time.perf_counter() - t0),
-          file=sys.stderr, flush=True)
-    dg = scc.to_device(g, "cuda:0")
-    out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
-    opts = scc.default_options(timing=0, validate=0, policy=args.policy)
-    if args.tau:
-        opts.tau = args.tau
-    if args.policy == 1:
-        import numpy as np
-        scc.policy_load(np.load(os.path.join(ROOT, "paper_2303_04934_amd", "policy_weights.npy")))
-    # Untimed warm-up.  Its last call times every frontier kernel to find the
-    # dominant one; the timed steps then bracket only that kernel's launches
-    # with events (each event pair costs a little, so the others run bare).
-    for i in range(max(args.warmup, 1)):
-        opts.timing = (1 << NK) - 1 if i == max(args.warmup, 1) - 1 else 0
-        _, st = scc.scc_labels(dg, opts, out=out, return_stats=True)
-    dom = max(range(NK), key=lambda i: st["ms_kernel"][i])
-    probe_ms = list(st["ms_kernel"])
-    opts.timing = 1 << dom
-    torch.cuda.synchronize()
-    print("[bench] warmup done; dominant frontier kernel %s" % KERNEL_NAMES[dom], file=sys.stderr, flush=True)
-
-    ms_exp = [0.0] * NK
-    launches = [0] * NK
-    bexp = [0] * NK
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = scc.scc_labels(dg, opts, return_stats=True, out=out)
-        stats.append(st)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    for st in stats:
-        for m in range(NK):
-            ms_exp[m] += st["ms_kernel"][m]
-            launches[m] += st["launches_kernel"][m]
-            bexp[m] += st["bytes_kernel"][m]
-    got = out.cpu().numpy()
-    print("[bench] timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3), file=sys.stderr, flush=True)
-
-    line = {
-        "metric": METRIC, "value": g.m / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "n": g.n, "m": g.m, "seed": 1000 + cfg,
-                   "tau": opts.tau, "policy": "learned" if args.policy == 1 else "fixed",
-                   "shrink": args.shrink},
-    }
-    if launches[dom] > 0 and ms_exp[dom] > 0:
-        per_launch_ms = ms_exp[dom] / launches[dom]
-        per_launch_bytes = bexp[dom] / launches[dom]
-        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-        traffic = load_traffic(args.workload, dom)
-        line["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                            "avg_launch_ms": per_launch_ms, "launches_per_step": launches[dom] / args.steps,
-                            "alg_bytes_per_launch": per_launch_bytes,
-                            "kernel_share_of_step": ms_exp[dom] / args.steps / (dt * 1e3)}
-    last = stats[-1]
-    line["stats"] = {k: last[k] for k in ("ms_trim", "ms_first", "ms_multi", "ms_resize", "ms_label", "batches",
-                                         "rounds_first", "rounds_multi", "dense_rounds", "trimmed", "n_scc",
-                                         "arcs_scanned",
-                                         "claims", "bag_inserts", "table_restarts", "bytes_alg")}
-    line["stats"]["alg_GBps_whole_step"] = last["bytes_alg"] / dt / 1e9
-    # every frontier kernel's event time in the (untimed) warm-up call that picked the dominant one
-    line["stats"]["kernel_ms_warmup_call"] = {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)}
-    if not args.no_cpu_baseline:
-        want, cb = cpu_baseline(g, args.cpu_runs)
-        line["cpu_baseline"] = cb
-        ok = bool(np.array_equal(got, want))
-        line["parity"] = "bit-exact vs oracle" if ok else "MISMATCH vs oracle"
-    print(json.dumps(line), flush=True)
-    if line.get("parity", "").startswith("MISMATCH"):
-        sys.exit(1)
+    else:
+        run_single(args, cfg, desc)
 
 
 if __name__ == "__main__":

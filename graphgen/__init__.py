@@ -8,6 +8,8 @@ The workload shapes stand in for the paper's evaluation graphs (Section 6:
 lattices, social/web graphs, k-NN graphs), which are not available here:
 
 * ``torus``/``grid``  -- 2-D lattice, every neighbour arc kept with p;
+* ``lattice_oriented`` -- the paper's SQR/REC (mode 0) and SQR'/REC' (mode 1)
+  tori with randomly oriented edges (Section 6);
 * ``rmat``            -- R-MAT (a, b, c, d) digraph, dedup, random ids;
 * ``knn``             -- directed k-NN graph of a 3-D Gaussian mixture;
 * ``batched``         -- many graphs with log-uniform sizes, family mixed.
@@ -53,6 +55,7 @@ def _load():
         P = ctypes.POINTER
         lib.gg_lattice.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_uint64, P(_Csr)]
+        lib.gg_lattice_oriented.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, P(_Csr)]
         lib.gg_rmat.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_uint64, ctypes.c_int, P(_Csr)]
         lib.gg_knn.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
@@ -125,6 +128,16 @@ def grid(rows: int, cols: int, p: float = 0.5, seed: int = 1003) -> Graph:
     return lattice(rows, cols, p, seed, False)
 
 
+def lattice_oriented(rows: int, cols: int, mode: int, seed: int) -> Graph:
+    """The paper's lattices (Section 6), a rows x cols torus: mode 0 = SQR/REC
+    (each endpoint draws an orientation for each of its edges, duplicates
+    removed), mode 1 = SQR'/REC' (each arc of each edge kept independently
+    with probability 0.3)."""
+    c = _Csr()
+    _check(_load().gg_lattice_oriented(rows, cols, mode, seed, ctypes.byref(c)), "gg_lattice_oriented")
+    return _finish(c, "%s%dx%d" % ("olat" if mode == 0 else "olat2_", rows, cols))
+
+
 def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
          seed: int = 1001, permute: bool = True) -> Graph:
     cs = _Csr()
@@ -188,6 +201,10 @@ CONFIG_NAMES = [
     "knn_10M_k5",          # 2: 3-D Gaussian-mixture k-NN, 1e7 points, 1000 centres
     "grid10000_p0.5",      # 3: 2-D grid 10000x10000 (no wrap), p=0.5
     "batched4096",         # 4: 4096 mixed graphs, log-uniform sizes in [1e3, 1e6]
+    "sqr_10000",           # 5: the paper's SQR, 10^4 x 10^4 torus, random orientations
+    "rec_1000x10000",      # 6: the paper's REC, 10^3 x 10^4 torus
+    "sqr2_10000",          # 7: the paper's SQR', each arc of an edge kept with p=0.3
+    "rec2_1000x10000",     # 8: the paper's REC'
 ]
 
 
@@ -205,6 +222,12 @@ def config(i: int, shrink: int = 0) -> Graph:
     if i == 3:
         side = max(3, int(round(10000 / math.sqrt(2 ** shrink))))
         return grid(side, side, 0.5, seed)
+    if i in (5, 7):  # SQR, SQR': 10^4 x 10^4
+        side = max(3, int(round(10000 / math.sqrt(2 ** shrink))))
+        return lattice_oriented(side, side, 0 if i == 5 else 1, seed)
+    if i in (6, 8):  # REC, REC': 10^3 x 10^4
+        f = math.sqrt(2 ** shrink)
+        return lattice_oriented(max(3, int(round(1000 / f))), max(3, int(round(10000 / f))), 0 if i == 6 else 1, seed)
     raise ValueError("config %d is a batch; use batched()" % i)
 
 

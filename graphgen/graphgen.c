@@ -198,6 +198,68 @@ int gg_lattice(int64_t rows, int64_t cols, int wrap, double p, uint64_t seed, gg
     return rc;
 }
 
+/* The paper's lattices (Section 6): a rows x cols torus (circular rows and
+ * columns), vertex id = r * cols + c, every lattice edge oriented at random.
+ *   mode 0 (SQR, REC): every vertex u draws, for each of its four adjacent
+ *     vertices v, an orientation: u -> v with probability 1/2, else v -> u;
+ *     duplicates are removed.  Each edge gets two draws (one per endpoint),
+ *     so it carries both arcs with probability 1/2: 1.5 arcs per edge, the
+ *     300M arcs Table 3 lists for the 10^4 x 10^4 SQR.
+ *   mode 1 (SQR', REC'): each edge carries each of its two arcs
+ *     independently with probability 0.3: 0.6 arcs per edge, Table 3's 120M
+ *     arcs for SQR' (the text's "no edge with probability 0.4" does not fit
+ *     independent arcs; this reading reproduces Table 3's arc count and its
+ *     share of SCCs, 78% of the vertices).  The edge between u and its east
+ *     (south) neighbour v belongs to u: u -> v is drawn at index 4u + 0
+ *     (4u + 2), v -> u at 4u + 1 (4u + 3).
+ * Draws: unif(seed, 2, 4u + d) for mode 0 (d in E, W, S, N order),
+ * unif(seed, 3, index above) for mode 1. */
+int gg_lattice_oriented(int64_t rows, int64_t cols, int mode, uint64_t seed, gg_csr *out) {
+    int64_t n = rows * cols;
+    if (rows <= 0 || cols <= 0 || n >= ((int64_t)1 << 31) || (mode != 0 && mode != 1)) return -3;
+    int64_t *soff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t *sadj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(4 * n));
+    int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!soff || !sadj || !deg) { free(soff); free(sadj); free(deg); return -1; }
+#pragma omp parallel for schedule(static)
+    for (int64_t u = 0; u < n; u++) {
+        const int64_t r = u / cols, c = u % cols;
+        const int64_t nb[4] = {r * cols + (c + 1) % cols, r * cols + (c + cols - 1) % cols,
+                               ((r + 1) % rows) * cols + c, ((r + rows - 1) % rows) * cols + c};
+        static const int opp[4] = {1, 0, 3, 2};
+        int64_t k = 0;
+        for (int d = 0; d < 4; d++) {
+            const int64_t v = nb[d];
+            int keep;
+            if (mode == 0) {
+                /* u -> v if u's draw for v says so, or v's draw for u says v <- u */
+                keep = unif(seed, 2, (uint64_t)(4 * u + d)) < 0.5 || unif(seed, 2, (uint64_t)(4 * v + opp[d])) >= 0.5;
+            } else if (d == 0 || d == 2) {
+                /* u owns the edge to its east / south neighbour: its forward arc */
+                keep = unif(seed, 3, (uint64_t)(4 * u + (d == 2 ? 2 : 0))) < 0.3;
+            } else {
+                /* the west / north neighbour v owns the edge: its backward arc v <- u */
+                keep = unif(seed, 3, (uint64_t)(4 * v + (d == 3 ? 3 : 1))) < 0.3;
+            }
+            if (keep) sadj[4 * u + k++] = (int32_t)v;
+        }
+        deg[u] = k;
+    }
+    int64_t tot = 0;
+    for (int64_t u = 0; u < n; u++) { soff[u] = tot; tot += deg[u]; }
+    soff[n] = tot;
+    int32_t *sadj2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tot > 0 ? tot : 1));
+    if (!sadj2) { free(soff); free(sadj); free(deg); return -1; }
+#pragma omp parallel for schedule(static)
+    for (int64_t u = 0; u < n; u++) memcpy(sadj2 + soff[u], sadj + 4 * u, sizeof(int32_t) * (size_t)deg[u]);
+    free(sadj);
+    free(deg);
+    int rc = compact_sorted(n, soff, sadj2, 1, out);
+    free(soff);
+    free(sadj2);
+    return rc;
+}
+
 /* --------------------------------------------------------------- R-MAT ---- */
 /* Arc i picks, level by level from the most significant bit, one of four
  * quadrants with probabilities (a, b, c, d = 1-a-b-c).  Each level consumes a

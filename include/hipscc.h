@@ -76,7 +76,10 @@ typedef struct {
  *                threads).  0 (default) = automatic: up to 2^20 slots, so that
  *                thousands of inserting wavefronts spread over many stripes.
  *   sigma        samples that trigger a hash bag chunk advance (Table 1: 50).
- *   kappa        stripe probes before an insert forces a chunk advance.
+ *   kappa        stripe probes before an insert forces a chunk advance (each
+ *                probe tries another random stripe of the current chunk;
+ *                default 32, so that the sampled load estimate, not the probe
+ *                limit, moves the chunk, as Section 3.3 intends).
  *   alpha        target load factor of a bag chunk (0 < alpha < 1).
  *   seed         seed of the random vertex permutation.
  *   policy       0 = fixed schedule, 1 = learned per-round policy (needs
@@ -122,7 +125,23 @@ typedef struct {
  *                (entries x average degree) than vgc_fill x the lanes of the
  *                expand grid; a frontier above that keeps the GPU busy on its
  *                own and runs as a plain round (0 = default 2; < 0 = cut at
- *                one entry per wavefront). */
+ *                one entry per wavefront).
+ *   union_arcs_max  scc_labels_batched: most arcs one disjoint union of
+ *                consecutive graphs may hold (0 = default 2^31 - 1, the int32
+ *                arc-index limit).  A smaller value splits a batch into more
+ *                unions; used to exercise the split on small batches.
+ *   first_slot   1 = multi-source searches claim each vertex's first pair in
+ *                a per-vertex slot (4 bytes at the vertex, next to its label)
+ *                and only later pairs in the reach table; 0 = every pair in
+ *                the table (Section 4.3).  Section 3.2 leaves the reach
+ *                record open; the slot replaces most random table probes
+ *                with an access at the vertex itself.
+ *   vgc_measure  what the VGC budget tau counts (Section 3.2 names
+ *                alternatives to examined arcs): 0 = examined arcs (default),
+ *                1 = new claims (generated reachability pairs, or visited
+ *                vertices for a single source).
+ *   ldd_beta     scc_cc: growth of the centre batches of the low-diameter
+ *                decomposition per round (Section 5.1 uses 1.2; default). */
 typedef struct {
     int32_t tau;
     float beta;
@@ -143,7 +162,10 @@ typedef struct {
     float vgc_fill;
     float beta_fast;
     float table_floor;
-    int32_t reserved[1];
+    int32_t union_arcs_max;
+    int32_t first_slot;
+    int32_t vgc_measure;
+    float ldd_beta;
 } scc_options_t;
 
 /* Frontier kernels timed with options.timing. */
@@ -174,6 +196,7 @@ typedef struct {
     int64_t bag_inserts;      /* hash bag inserts */
     int64_t bag_chunk_advances;
     int64_t table_restarts;   /* searches re-run with a larger table */
+    int64_t restart_rounds;   /* rounds of the attempts those restarts abandoned */
     int64_t trimmed;          /* vertices finished by trimming */
     int64_t n_scc;            /* number of SCCs (scc_labels only) */
     int64_t policy_calls;     /* rounds decided by the learned policy */
@@ -218,8 +241,9 @@ scc_status scc_labels(scc_ctx_t *ctx, const scc_graph_t *g, int32_t *labels_out,
  * int32[n]; an arc (u, w) is used only if labels[u] == labels[w] (Algorithm 1
  * skips arcs whose endpoints have different labels); vertices with a negative
  * label are excluded.  Output: every pair (v, j) with sources[j] ~> v,
- * including (sources[j], j), exactly once, in unspecified order, written as
- * pairs_out[2*i] = v, pairs_out[2*i+1] = j (device int32[2 * capacity]).
+ * including (sources[j], j), exactly once, sorted ascending by (j, v) (the
+ * sort runs on the device), written as pairs_out[2*i] = v,
+ * pairs_out[2*i+1] = j (device int32[2 * capacity]).
  * *n_pairs (host) always receives the number of pairs; if it exceeds
  * capacity the call returns SCC_ECAPACITY and pairs_out is unspecified.
  * With k == 1 the single-source (visited-flag) search is used. */
@@ -242,6 +266,22 @@ scc_status scc_labels_batched(scc_ctx_t *ctx, int32_t G, const int64_t *vtx_base
                               const int32_t *out_off, const int32_t *out_adj, const int32_t *in_off,
                               const int32_t *in_adj, int32_t *labels_out, const scc_options_t *opt,
                               scc_stats_t *stats);
+
+/* Connected components (Section 5.1, Algorithm 4, LDD-UF-JTB).  Only the
+ * out-CSR of g is read (in_off / in_adj may be NULL).  A low-diameter
+ * decomposition assigns every vertex to a cluster centre: centres are added
+ * in random order in batches growing by options.ldd_beta per round, and
+ * every round searches out from the frontier with VGC (budget options.tau)
+ * and the hash bag; a concurrent union-find then merges the clusters joined
+ * by an arc.  labels_out: device int32[n]; on return labels_out[v] is the
+ * smallest vertex id of v's weakly connected component, i.e. of its
+ * connected component when g is symmetric (every arc has its reverse), the
+ * undirected graphs the paper runs this on.  Stats: ms_first = the
+ * decomposition, ms_label = union-find and labels, rounds_first = its
+ * search rounds, n_scc = the number of components, arcs_scanned and
+ * claim_attempts include the union pass's arcs and link attempts. */
+scc_status scc_cc(scc_ctx_t *ctx, const scc_graph_t *g, int32_t *labels_out, const scc_options_t *opt,
+                  scc_stats_t *stats);
 
 /* Load the learned round policy: a float32 MLP 5 -> 32 -> 32 -> 8 with ReLU,
  * weights as one host blob [W1(32x5), b1(32), W2(32x32), b2(32), W3(8x32),
@@ -276,6 +316,20 @@ scc_status scc_trace_read(scc_ctx_t *ctx, float *out, int64_t cap, int64_t *n_ro
  * structure is correct.  Stats report chunk advances.  Test hook. */
 scc_status scc_bag_selftest(scc_ctx_t *ctx, const uint64_t *keys, int64_t n, int32_t rounds, uint64_t *out,
                             int64_t *n_out, const scc_options_t *opt, scc_stats_t *stats);
+
+/* Statistics of the last scc_bag_selftest on this context, for the bounds of
+ * Theorem 1 (Section 3.3, Appendix A): with alpha = 1/2 a chunk is left at a
+ * load within [1/4, 3/4] w.h.p., and s elements occupy a prefix of
+ * O(s + lambda) slots.  rows: host double[4 * cap], one row (round, chunk,
+ * load, cause) per chunk that was left during a round, load = its filled
+ * slots / its size when that round's ExtractAll ran (late inserts of waves
+ * that read the old chunk included), cause = 0 when its samples reached
+ * sigma, 1 when an insert exceeded kappa stripe probes; *n_rows receives the
+ * row count.  prefix: host
+ * int64[prefix_cap], the used prefix (tail of the current chunk) at each
+ * round's ExtractAll; *n_rounds receives the round count.  Test hook. */
+scc_status scc_bag_stats(scc_ctx_t *ctx, double *rows, int64_t cap, int64_t *n_rows, int64_t *prefix,
+                         int64_t prefix_cap, int64_t *n_rounds);
 
 #ifdef __cplusplus
 }

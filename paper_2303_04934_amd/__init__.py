@@ -19,8 +19,8 @@ import numpy as np
 from . import _native
 from ._native import POLICY_FLOATS, STATUS_NAMES, Options, Stats
 
-__all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_reach",
-           "scc_labels_batched", "bag_selftest", "policy_load", "policy_eval", "trace_read", "version",
+__all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_cc", "scc_reach",
+           "scc_labels_batched", "bag_selftest", "bag_stats", "policy_load", "policy_eval", "trace_read", "version",
            "POLICY_FLOATS", "TRACE_FIELDS"]
 
 TRACE_FIELDS = _native.TRACE_FIELDS
@@ -118,10 +118,28 @@ def scc_labels(dg: DeviceGraph, options: Options | None = None, return_stats: bo
     return (out, st.as_dict()) if return_stats else out
 
 
+def scc_cc(dg: DeviceGraph, options: Options | None = None, return_stats: bool = False, out=None):
+    """Connected components (LDD-UF-JTB): smallest vertex id of each vertex's
+    weakly connected component, int32 tensor [n].  Reads the out-CSR only."""
+    torch = _torch()
+    lib = _native.load()
+    ctx = _current(dg.out_off)
+    if out is None:
+        out = torch.empty(max(dg.n, 1), dtype=torch.int32, device=dg.out_off.device)
+    st = Stats()
+    g = dg.c_struct()
+    rc = lib.scc_cc(ctx, ctypes.byref(g), out.data_ptr(), ctypes.byref(options) if options else None,
+                    ctypes.byref(st))
+    _check(lib, ctx, rc)
+    out = out[:dg.n]
+    return (out, st.as_dict()) if return_stats else out
+
+
 def scc_reach(dg: DeviceGraph, sources, labels, direction: int = 0, capacity: int | None = None,
               options: Options | None = None, return_stats: bool = False):
     """Reachability pairs (vertex, source index) as an int32 tensor [count, 2],
-    in unspecified order.  Arcs are used only between equal, non-negative labels."""
+    sorted ascending by (source index, vertex) on the device.  Arcs are used
+    only between equal, non-negative labels."""
     torch = _torch()
     lib = _native.load()
     dev = dg.out_off.device
@@ -182,6 +200,23 @@ def bag_selftest(keys, rounds: int = 1, options: Options | None = None, return_s
     _check(lib, ctx, rc)
     out = out[:cnt.value]
     return (out, st.as_dict()) if return_stats else out
+
+
+def bag_stats(device_index: int = 0):
+    """Statistics of the last bag_selftest on the current stream's context:
+    (rows [r, 4] of (round, chunk, load, cause) for every chunk left during a
+    round, cause 0 = samples reached sigma, 1 = probe limit; used prefix per
+    round)."""
+    torch = _torch()
+    lib = _native.load()
+    ctx = _ctx(device_index, torch.cuda.current_stream(device_index).cuda_stream)
+    nr, nq = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib, ctx, lib.scc_bag_stats(ctx, None, 0, ctypes.byref(nr), None, 0, ctypes.byref(nq)))
+    rows = np.zeros((max(int(nr.value), 1), 4), np.float64)
+    prefix = np.zeros(max(int(nq.value), 1), np.int64)
+    _check(lib, ctx, lib.scc_bag_stats(ctx, rows.ctypes.data, int(nr.value), ctypes.byref(nr), prefix.ctypes.data,
+                                       int(nq.value), ctypes.byref(nq)))
+    return rows[:int(nr.value)], prefix[:int(nq.value)]
 
 
 def trace_read(device_index: int = 0):

@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("trim", ctypes.c_int32), ("table_init", ctypes.c_int64),
                 ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float),
-                ("beta_fast", ctypes.c_float), ("table_floor", ctypes.c_float), ("reserved", ctypes.c_int32 * 1)]
+                ("beta_fast", ctypes.c_float), ("table_floor", ctypes.c_float), ("union_arcs_max", ctypes.c_int32),
+                ("first_slot", ctypes.c_int32), ("vgc_measure", ctypes.c_int32), ("ldd_beta", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -40,7 +41,7 @@ class Stats(ctypes.Structure):
                                                 "ms_label")] + \
                [(f, ctypes.c_int64) for f in ("n", "m", "batches", "rounds_first", "rounds_multi", "dense_rounds",
                                                "entries_expanded", "arcs_scanned", "claim_attempts", "claims",
-                                               "bag_inserts", "bag_chunk_advances", "table_restarts", "trimmed",
+                                               "bag_inserts", "bag_chunk_advances", "table_restarts", "restart_rounds", "trimmed",
                                                "n_scc", "policy_calls", "policy_fallbacks", "bytes_alg")] + \
                [("ms_kernel", ctypes.c_double * KERNELS), ("launches_kernel", ctypes.c_int64 * KERNELS),
                 ("bytes_kernel", ctypes.c_int64 * KERNELS)]
@@ -48,8 +49,6 @@ class Stats(ctypes.Structure):
     def as_dict(self):
         d = {}
         for f, _ in self._fields_:
-            if f == "reserved":
-                continue
             v = getattr(self, f)
             d[f] = list(v) if hasattr(v, "__len__") else v
         return d
@@ -57,7 +56,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["scc_version", "scc_default_options", "scc_create", "scc_destroy", "scc_last_error", "scc_labels",
            "scc_reach", "scc_labels_batched", "scc_policy_load", "scc_policy_eval", "scc_bag_selftest",
-           "scc_trace_read"]
+           "scc_trace_read", "scc_bag_stats", "scc_cc"]
 TRACE_FIELDS = 12
 
 _lib = None
@@ -81,12 +80,14 @@ def load():
     lib.scc_last_error.argtypes = [vp]
     lib.scc_last_error.restype = ctypes.c_char_p
     lib.scc_labels.argtypes = [vp, P(Graph), vp, P(Options), P(Stats)]
+    lib.scc_cc.argtypes = [vp, P(Graph), vp, P(Options), P(Stats)]
     lib.scc_reach.argtypes = [vp, P(Graph), i32, vp, i32, vp, vp, i64, P(i64), P(Options), P(Stats)]
     lib.scc_labels_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, P(Options), P(Stats)]
     lib.scc_policy_load.argtypes = [vp, vp, i64]
     lib.scc_policy_eval.argtypes = [vp, vp, i32, vp]
     lib.scc_bag_selftest.argtypes = [vp, vp, i64, i32, vp, P(i64), P(Options), P(Stats)]
     lib.scc_trace_read.argtypes = [vp, vp, i64, P(i64)]
+    lib.scc_bag_stats.argtypes = [vp, vp, i64, P(i64), vp, i64, P(i64)]
     for name in EXPORTS:
         if name not in ("scc_version", "scc_destroy", "scc_last_error"):
             getattr(lib, name).restype = ctypes.c_int32

@@ -8,9 +8,12 @@ it.  None of them changes the labels, only rounds and work, and the best
 values depend on the graphs (k-NN graphs and short-diameter graphs gain from
 fast batch growth, long lattices lose) and on the batch's size: beta sets how
 many source batches a run takes, log_beta(n), so a sample must keep the
-scale of the whole batch.  The tuner times a few candidate schedules on a sample of the
-batch (every k-th graph; by default every second one), on the GPU, and
-returns the fastest as options for the whole batch.
+scale of the whole batch.  The tuner times a few candidate schedules on a
+sample of the batch (every k-th graph, k >= 2, from a seeded offset; by
+default every second graph, a strict subset that keeps the batch's scale), on
+the GPU, and returns the fastest as options for the whole batch.  It then
+times the chosen schedule and the default one on the graphs it did not see,
+so that the reported gain is measured out of sample.
 
 All timing goes through the library's C ABI; this module only chooses
 which options to pass.
@@ -23,9 +26,11 @@ import numpy as np
 
 from . import _native
 
-# candidate (tau, beta, beta_fast) schedules: the defaults first
-CANDIDATES = [(2048, 2.0, 8.0), (2048, 2.0, 24.0), (4096, 2.0, 8.0), (2048, 3.0, 8.0), (4096, 2.0, 24.0),
-              (1024, 2.0, 16.0)]
+# candidate (tau, beta, beta_fast, policy) schedules, the defaults first;
+# policy 1 lets the learned per-round policy pick the budget (tau is then its
+# fallback), so the tuner also decides whether the policy is used
+CANDIDATES = [(2048, 2.0, 8.0, 0), (2048, 2.0, 24.0, 0), (4096, 2.0, 8.0, 0), (2048, 3.0, 8.0, 0),
+              (4096, 2.0, 24.0, 0), (1024, 2.0, 16.0, 0), (2048, 2.0, 8.0, 1), (2048, 2.0, 24.0, 1)]
 
 
 def _subset(vb, ab, arrays, idx):
@@ -49,49 +54,84 @@ def _subset(vb, ab, arrays, idx):
     return vb2, ab2, (cat(po), cat(pa), cat(pi), cat(pia))
 
 
-def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = None, repeats: int = 1,
-         candidates=CANDIDATES, base_options=None, verbose: bool = False):
-    """Pick (tau, beta, beta_fast) for a batch.  Returns (options, report)
-    where report lists each candidate's best sample time in ms."""
+def _time_batch(vb, ab, arrs, o, repeats):
     import torch
 
-    from . import default_options, scc_labels_batched
+    from . import scc_labels_batched
+    ts = []
+    for r in range(repeats + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        scc_labels_batched(vb, ab, *arrs, options=o)
+        torch.cuda.synchronize()
+        if r:  # the first call warms up (allocations)
+            ts.append((time.perf_counter() - t0) * 1e3)
+    return min(ts)
+
+
+def split(vb, ab, sample_arcs: int | None = None, seed: int = 0):
+    """Indices of the tuning sample and of the held-out graphs: every k-th
+    graph from a seeded offset, k = max(2, total arcs // sample_arcs)."""
     vb = np.asarray(vb, np.int64)
     ab = np.asarray(ab, np.int64)
     G = len(vb) - 1
-    total = int(ab[-1])
+    total = int(ab[-1]) if G else 0
     if sample_arcs is None:
-        sample_arcs = (total + 1) // 2
-    stride = max(1, int(total // max(sample_arcs, 1)))
-    idx = list(range(0, G, stride)) if G else []
-    svb, sab, sarr = _subset(vb, ab, (out_off, out_adj, in_off, in_adj), idx)
+        sample_arcs = total // 2
+    stride = max(2, int(total // max(sample_arcs, 1)))
+    off = int(np.random.default_rng(seed).integers(0, stride)) if G else 0
+    idx = list(range(off, G, stride))
+    seen = set(idx)
+    rest = [g for g in range(G) if g not in seen]
+    return idx, rest
+
+
+def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = None, repeats: int = 1,
+         candidates=CANDIDATES, base_options=None, verbose: bool = False, seed: int = 0, held_out: bool = True):
+    """Pick (tau, beta, beta_fast, policy) for a batch.  Returns (options, report):
+    each candidate's best time on the sample, and (held_out) the chosen and
+    the default schedule's times on the graphs outside the sample."""
+    from . import default_options
+    vb = np.asarray(vb, np.int64)
+    ab = np.asarray(ab, np.int64)
+    arrays = (out_off, out_adj, in_off, in_adj)
+    idx, rest = split(vb, ab, sample_arcs, seed)
+    svb, sab, sarr = _subset(vb, ab, arrays, idx)
     report = []
     best = None
-    for tau, beta, beta_fast in candidates:
+    for cand in candidates:
+        tau, beta, beta_fast = cand[:3]
+        policy = cand[3] if len(cand) > 3 else 0
         o = default_options() if base_options is None else _copy(base_options)
         o.tau = tau
         o.beta = beta
         o.beta_fast = beta_fast
+        o.policy = policy
         o.timing = 0
-        ts = []
-        for r in range(repeats + 1):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            scc_labels_batched(svb, sab, *sarr, options=o)
-            torch.cuda.synchronize()
-            if r:  # the first call warms up (allocations)
-                ts.append((time.perf_counter() - t0) * 1e3)
-        ms = min(ts)
-        report.append({"tau": tau, "beta": beta, "beta_fast": beta_fast, "sample_ms": ms})
+        ms = _time_batch(svb, sab, sarr, o, repeats)
+        report.append({"tau": tau, "beta": beta, "beta_fast": beta_fast, "policy": policy, "sample_ms": ms})
         if verbose:
-            print("[autotune] tau=%d beta=%.1f beta_fast=%.0f sample %.2f ms" % (tau, beta, beta_fast, ms),
-                  flush=True)
+            print("[autotune] tau=%d beta=%.1f beta_fast=%.0f policy=%d sample %.2f ms" %
+                  (tau, beta, beta_fast, policy, ms), flush=True)
         if best is None or ms < best[0]:
-            best = (ms, tau, beta, beta_fast)
+            best = (ms, tau, beta, beta_fast, policy)
+    del sarr
     o = default_options() if base_options is None else _copy(base_options)
     if best is not None:
-        o.tau, o.beta, o.beta_fast = best[1], best[2], best[3]
-    return o, {"sample_graphs": len(idx), "sample_arcs": int(sab[-1]) if len(idx) else 0, "candidates": report}
+        o.tau, o.beta, o.beta_fast, o.policy = best[1], best[2], best[3], best[4]
+    rep = {"sample_graphs": len(idx), "sample_arcs": int(sab[-1]) if len(idx) else 0,
+           "held_out_graphs": len(rest), "candidates": report}
+    if held_out and rest:
+        hvb, hab, harr = _subset(vb, ab, arrays, rest)
+        d = default_options() if base_options is None else _copy(base_options)
+        d.timing = 0
+        d.policy = 0
+        o.timing = 0
+        rep["held_out_tuned_ms"] = _time_batch(hvb, hab, harr, o, repeats)
+        rep["held_out_default_ms"] = _time_batch(hvb, hab, harr, d, repeats)
+        rep["held_out_arcs"] = int(hab[-1])
+        del harr
+    return o, rep
 
 
 def _copy(o):

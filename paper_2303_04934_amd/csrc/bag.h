@@ -13,9 +13,9 @@
 // a wavefront inserts its elements together: each chunk is cut into stripes
 // of kStripe slots with one fill counter each; the wave picks a random stripe
 // of chunk r and reserves room for all its elements with one fetch-and-add on
-// that counter, spilling the remainder to the next stripe (the probe).  After
-// kappa probes the insert forces a chunk advance, as the paper's probe limit
-// does.  A stripe's valid slots are exactly [0, min(count, kStripe)), so
+// that counter, spilling the remainder to another random stripe (the probe).
+// After kappa probes the insert forces a chunk advance, as the paper's probe
+// limit does.  A stripe's valid slots are exactly [0, min(count, kStripe)), so
 // ExtractAll reads counters instead of scanning for empty slots, and clearing
 // resets counters only.  Random stripe choice spreads the atomics over many
 // addresses; sampling keeps the chunk advance off the common path.
@@ -36,6 +36,11 @@ struct BagCtl {
     uint32_t overflow;             // set when the last chunk is full
     uint32_t advances;             // chunk advances (statistics)
     uint32_t sample[kMaxChunks];   // samples taken per chunk
+    // statistics of the bag self test (Bag::track): slots filled per chunk,
+    // counted by ExtractAll, and the chunk that was current when it ran
+    uint32_t fill[kMaxChunks];
+    uint32_t last_r;
+    uint64_t forced;               // bit i: chunk i was left by the probe limit, not by samples
 };
 
 struct Bag {
@@ -48,7 +53,14 @@ struct Bag {
     uint32_t kappa;
     float alpha;
     uint32_t salt;       // varies per round: decorrelates stripe choice and sampling
+    uint32_t track;      // 1: ExtractAll also counts the filled slots of each chunk (self test)
 };
+
+// Chunk that holds stripe st (stripe st covers slots [64 st, 64 st + 64)).
+__host__ __device__ __forceinline__ uint32_t bag_chunk_of_stripe(const Bag &B, uint64_t st) {
+    const uint64_t q = (st << kStripeLog2) >> B.lam_log2;
+    return q == 0 ? 0u : 64u - (uint32_t)__builtin_clzll(q);
+}
 
 __host__ __device__ __forceinline__ uint64_t bag_chunk_lo(const Bag &B, uint32_t i) {
     return i == 0 ? 0ull : (1ull << (B.lam_log2 + i - 1));
@@ -133,11 +145,20 @@ __device__ __forceinline__ int bag_insert_wave_n(const Bag &B, const bool (&has)
                     B.slots[((uint64_t)(st0 + st) << kStripeLog2) + o + (uint32_t)(my[j] - placed)] = e[j];
             placed += avail;
             if (placed < k) {
-                st = (st + 1 == nst) ? 0 : st + 1;
+                // the next probe: a fresh random stripe (no primary clustering,
+                // so a long run of full stripes stays as unlikely as the load
+                // makes it), except in the last chunk, which never advances
+                // and walks its stripes in order until every one was tried
+                if (last) st = (st + 1 == nst) ? 0 : st + 1;
+                else st = (uint32_t)(mix64(((uint64_t)wave_gid << 32) ^ (uint64_t)(wseq++) ^ ((uint64_t)B.salt << 20) ^
+                                           0xD1B54A32D192ED03ull) % nst);
                 probes++;
                 if (!last && probes > B.kappa) {
                     if (lane_id() == 0) {
-                        if (atomicCAS(&B.ctl->r, r, r + 1) == r) atomicAdd(&B.ctl->advances, 1u);
+                        if (atomicCAS(&B.ctl->r, r, r + 1) == r) {
+                            atomicAdd(&B.ctl->advances, 1u);
+                            atomicOr((unsigned long long *)&B.ctl->forced, 1ull << r);
+                        }
                     }
                     spill = true;
                     break;

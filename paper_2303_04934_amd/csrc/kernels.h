@@ -109,17 +109,24 @@ constexpr int kQmask = kQcap - 1;
 constexpr int kStepArcs = 256;  // arcs a wave commits to per local-search step
 constexpr int kHeavyChunk = 4096;  // arcs per edge-parallel work item
 
-enum { kSingle = 0, kMulti = 1 };
+enum { kSingle = 0, kMulti = 1, kMultiFirst = 2, kLdd = 3 };
 
 // One reachability search (one direction).  kSingle claims vertices in a
 // visited bitmap whose bits were pre-set for every vertex outside the search's
-// subproblem; kMulti claims (vertex, source) pairs in the reach table.
+// subproblem; kMulti claims (vertex, source) pairs in the reach table;
+// kMultiFirst claims the first pair of each vertex in a per-vertex slot
+// (first[v] = source index) and only later pairs in the reach table.  kLdd
+// is kSingle for the low-diameter decomposition of Algorithm 4: an entry
+// carries its cluster centre in place of the source index, and a claim also
+// records owner[w] = centre.
 struct Search {
     const int32_t *off;
     const int32_t *adj;
     const int32_t *label;   // kMulti: arc (u, w) is used iff label[w] == label of the source
     uint32_t *vis;          // kSingle
     uint64_t *table;        // kMulti
+    int32_t *first;         // kMultiFirst: per-vertex first-source slot (-1 = empty)
+    int32_t *owner;         // kLdd: cluster centre of each claimed vertex
     uint64_t tmask;
     uint32_t probe_limit;
     const int32_t *srclab;  // kMulti: label of source j
@@ -142,6 +149,7 @@ struct Search {
     const float *policy_w;  // non-null: ExtractAll's last block runs the policy for the next round
     float nsub;             // subproblem size (policy feature)
     uint32_t fallback_tau;  // budget when the policy's scores are unusable
+    int32_t measure;        // what the budget counts: 0 examined arcs, 1 new claims (pairs / visited vertices)
 };
 
 // ------------------------------------------------------------- utilities ----
@@ -407,6 +415,21 @@ __device__ __forceinline__ int claim_pair(uint64_t *T, uint64_t mask, uint32_t l
     return -1;
 }
 
+// A pair claim with the inline first-source slot: the slot of w holds the
+// first source that reached w; a pair of any other source goes to the table.
+// Returns like claim_pair.
+__device__ __forceinline__ int claim_pair_first(int32_t *first, uint64_t *T, uint64_t mask, uint32_t limit, int32_t w,
+                                                uint32_t src) {
+    const int32_t f = (int32_t)ld_relaxed(reinterpret_cast<const uint32_t *>(first + w));
+    if (f == (int32_t)src) return 0;
+    if (f == -1) {
+        const int32_t old = atomicCAS(first + w, -1, (int32_t)src);
+        if (old == -1) return 1;
+        if (old == (int32_t)src) return 0;
+    }
+    return claim_pair(T, mask, limit, pair_key(w, src));
+}
+
 __device__ __forceinline__ bool table_contains(const uint64_t *T, uint64_t mask, uint32_t limit, uint64_t key) {
     uint64_t h = mix64(key) & mask;
     for (uint32_t p = 0; p <= limit; p++) {
@@ -466,6 +489,7 @@ __global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_
 // in the lane's reach table and put it in its frontier.
 struct SeedArgs {
     uint64_t *T[2];
+    int32_t *first[2];      // non-null: the lane claims first pairs in per-vertex slots
     uint64_t mask[2];
     uint64_t *F[2];
     RoundCtl *rc[2];
@@ -479,7 +503,9 @@ __global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, SeedArgs 
     const uint32_t k = sh->k;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
         uint64_t key = pair_key(srcvert[j], j);
-        if (claim_pair(A.T[l], A.mask[l], limit, key) < 0) atomicOr(&rc->err, kErrTable);
+        const int c = A.first[l] ? claim_pair_first(A.first[l], A.T[l], A.mask[l], limit, srcvert[j], j)
+                                 : claim_pair(A.T[l], A.mask[l], limit, key);
+        if (c < 0) atomicOr(&rc->err, kErrTable);
         A.F[l][j] = key;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -528,9 +554,11 @@ __global__ void k_batch_reset(Shared *sh, RoundCtl *rc0, RoundCtl *rc1) {
 // its first reach-table probe and its offsets together.
 template <int MODE, int ILP>
 __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint32_t nblk) {
-    __shared__ uint64_t Qk[kWavesPerBlock][kQcap];                      // (vertex, source) keys
-    __shared__ int2 Qr[kWavesPerBlock][kQcap];                          // (first arc, degree)
-    __shared__ int32_t Ql[kWavesPerBlock][MODE == kMulti ? kQcap : 1];  // entry's label (kMulti)
+    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst;
+    constexpr bool FIRST = MODE == kMultiFirst;
+    __shared__ uint64_t Qk[kWavesPerBlock][kQcap];                 // (vertex, source) keys
+    __shared__ int2 Qr[kWavesPerBlock][kQcap];                     // (first arc, degree)
+    __shared__ int32_t Ql[kWavesPerBlock][PAIRS ? kQcap : 1];      // entry's label (multi-source)
     __shared__ int32_t Sx[kWavesPerBlock][4][kWave];
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -583,7 +611,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
             R[lane] = make_int2(b0, S.off[u + 1] - b0);
             // an entry (u, j) was claimed because label[u] equals source j's
             // label, so the entry carries the label its arcs are tested against
-            if (MODE == kMulti) QL[lane] = S.label[u];
+            if (PAIRS) QL[lane] = S.label[u];
         }
         c_seeds += (unsigned long long)cnt;
         int head = 0, tail = cnt;
@@ -606,7 +634,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                 beg = r2.x;
                 d = r2.y;
                 s = key_source(e);
-                if (MODE == kMulti) lab = QL[(head + lane) & kQmask];
+                if (PAIRS) lab = QL[(head + lane) & kQmask];
             }
             // candidate heavy entries (deferred to the edge-parallel kernel)
             bool hv = lane < k && d > S.heavy_deg;
@@ -653,7 +681,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                 slab[lane] = lab;
             }
             head += kk;
-            t += D;
+            if (S.measure == 0) t += D;
             c_exp += (mine && !hv) ? 1 : 0;
             wave_lds_sync();
             // The step's arcs, ILP per lane: every phase issues the memory
@@ -691,7 +719,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                         ne[j] = pair_key(w[j], (uint32_t)ssrc[lo_[j]]);
                         c_arcs++;
                     }
-                if (MODE == kSingle) {
+                if (!PAIRS) {
                     uint32_t old[ILP];
                     int32_t o0[ILP], o1[ILP];
                     if (vgc) {
@@ -724,20 +752,30 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                     }
 #pragma unroll
                     for (int j = 0; j < ILP; j++) c_att += va[j] ? 1 : 0;
+                    if (MODE == kLdd) {
+#pragma unroll
+                        for (int j = 0; j < ILP; j++)
+                            if (claimed[j]) S.owner[w[j]] = (int32_t)key_source(ne[j]);
+                    }
                 } else {
                     uint64_t h[ILP], cur[ILP];
-                    int32_t o0[ILP], o1[ILP];
+                    int32_t o0[ILP], o1[ILP], fs[ILP];
                     int st[ILP];  // 2: claim pending, 1: claimed, 0: present or skipped
 #pragma unroll
                     for (int j = 0; j < ILP; j++) {
                         h[j] = 0;
                         cur[j] = 0;
                         o0[j] = o1[j] = 0;
+                        fs[j] = -1;
                         nlab[j] = -1;
                         if (va[j]) {
-                            h[j] = mix64(ne[j]) & S.tmask;
                             nlab[j] = S.label[w[j]];
-                            cur[j] = ld_relaxed64(S.table + h[j]);
+                            if (FIRST) {
+                                fs[j] = (int32_t)ld_relaxed(reinterpret_cast<const uint32_t *>(S.first + w[j]));
+                            } else {
+                                h[j] = mix64(ne[j]) & S.tmask;
+                                cur[j] = ld_relaxed64(S.table + h[j]);
+                            }
                             if (vgc) {
                                 o0[j] = S.off[w[j]];
                                 o1[j] = S.off[w[j] + 1];
@@ -749,6 +787,33 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                         st[j] = (va[j] && nlab[j] == slab[lo_[j]]) ? 2 : 0;
                         c_att += st[j] == 2 ? 1 : 0;
                         nr[j] = make_int2(o0[j], o1[j] - o0[j]);
+                    }
+                    if (FIRST) {
+                        // the inline slot first: already this source's, free
+                        // (claim it), or another source's (the pair goes to the table)
+                        bool tab[ILP];
+#pragma unroll
+                        for (int j = 0; j < ILP; j++) {
+                            tab[j] = false;
+                            if (st[j] != 2) continue;
+                            const int32_t src = (int32_t)key_source(ne[j]);
+                            if (fs[j] == src) {
+                                st[j] = 0;
+                            } else if (fs[j] == -1) {
+                                const int32_t old = atomicCAS(S.first + w[j], -1, src);
+                                if (old == -1) st[j] = 1;
+                                else if (old == src) st[j] = 0;
+                                else tab[j] = true;
+                            } else {
+                                tab[j] = true;
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < ILP; j++)
+                            if (tab[j]) {
+                                h[j] = mix64(ne[j]) & S.tmask;
+                                cur[j] = ld_relaxed64(S.table + h[j]);
+                            }
                     }
                     // linear probing from the first slot (already loaded);
                     // every round of the loop is one load + one CAS per lane
@@ -802,6 +867,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                     tot += popc64(m);
                     c_claims += claimed[j] ? 1 : 0;
                 }
+                if (S.measure == 1) t += tot;
                 if (tot == 0) continue;
                 const int room = vgc ? kQcap - (tail - head) : 0;
                 bool tobag[ILP];
@@ -811,7 +877,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                         const int qi = (tail + rk[j]) & kQmask;
                         Q[qi] = ne[j];
                         R[qi] = nr[j];
-                        if (MODE == kMulti) QL[qi] = nlab[j];
+                        if (PAIRS) QL[qi] = nlab[j];
                     }
                     tobag[j] = claimed[j] && rk[j] >= room;
                 }
@@ -878,6 +944,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(LanePair P) {
 // its four waves stride over the slice; claims go to the bag.
 template <int MODE>
 __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint32_t nblk) {
+    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst;
     RoundCtl *rc = S.rc;
     uint32_t nh = ld_relaxed(&rc->heavy_n[S.par]);
     if (nh == 0) return;
@@ -897,7 +964,7 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
         const int64_t d = (int64_t)S.off[u + 1] - beg0;
         const int64_t lo = (int64_t)chunk * kHeavyChunk;
         const int64_t len = (d - lo) < kHeavyChunk ? (d - lo) : kHeavyChunk;
-        const int32_t lab = (MODE == kMulti) ? S.srclab[src] : 0;
+        const int32_t lab = PAIRS ? S.srclab[src] : 0;
         if (chunk == 0 && threadIdx.x == 0) c_exp++;
         for (int64_t base = (int64_t)wv * kWave; base < len; base += kBlock) {
             const int64_t a = base + lane;
@@ -906,12 +973,15 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
             if (a < len) {
                 const int32_t w = S.adj[beg0 + lo + a];
                 c_arcs++;
-                if (MODE == kSingle) {
+                if (!PAIRS) {
                     c_att++;
                     claimed = claim_bit(S.vis, w);
+                    if (MODE == kLdd && claimed) S.owner[w] = (int32_t)src;
                 } else if (S.label[w] == lab) {
                     c_att++;
-                    const int c = claim_pair(S.table, S.tmask, S.probe_limit, pair_key(w, src));
+                    const int c = MODE == kMultiFirst
+                                      ? claim_pair_first(S.first, S.table, S.tmask, S.probe_limit, w, src)
+                                      : claim_pair(S.table, S.tmask, S.probe_limit, pair_key(w, src));
                     if (c < 0) atomicOr(&rc->err, kErrTable);
                     claimed = c == 1;
                 }
@@ -923,7 +993,7 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
     }
     unsigned long long c[kNumCtr] = {0, c_exp, c_arcs, c_att, c_claims, c_ins};
     const unsigned long long t =
-        block_flush_ctr(S.cn->c[bid % kCtrStripes][MODE == kMulti ? kKindHeavyMulti : kKindHeavySingle], c);
+        block_flush_ctr(S.cn->c[bid % kCtrStripes][PAIRS ? kKindHeavyMulti : kKindHeavySingle], c);
     if (threadIdx.x == kCtrClaims && t) atomicAdd(&S.ls->s[bid % kStripes].claims, t);
 }
 
@@ -1129,7 +1199,10 @@ __device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t
                 }
             }
         }
-        if (st < nst && c) B.cnt[st] = 0;
+        if (st < nst && c) {
+            B.cnt[st] = 0;
+            if (B.track) atomicAdd(&B.ctl->fill[bag_chunk_of_stripe(B, st)], c);
+        }
     }
     {
         // the new frontier's degree sum (its offsets are read anyway by the
@@ -1151,6 +1224,7 @@ __device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t
 __device__ __forceinline__ void extract_reset(const Search &S, int par) {
     const Bag &B = S.bag;
     for (uint32_t i = 0; i < B.nchunks && i < (uint32_t)kMaxChunks; i++) B.ctl->sample[i] = 0;
+    B.ctl->last_r = B.ctl->r;
     B.ctl->r = 0;
     B.ctl->done_blocks = 0;
     S.rc->nF[par] = 0;
@@ -1233,20 +1307,28 @@ __global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, const Shar
 // not read it).
 __global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, uint64_t *Tin, uint64_t min_,
                              uint32_t limit, const int32_t *srcvert, unsigned long long *sig_out,
-                             unsigned long long *sig_in, int32_t *fin, bool clear_in) {
+                             unsigned long long *sig_in, int32_t *fin, bool clear_in, const int32_t *firstF,
+                             const int32_t *firstB) {
+    // with first-source slots a vertex's pairs are its slot plus its table
+    // keys, per direction; the slots themselves are summed by the per-vertex
+    // relabel, and a shared source is found here for every combination that
+    // involves a table key (slot/slot is the relabel's test)
     const uint64_t n_out = mout + 1, n_tot = n_out + min_ + 1;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_tot; i += (uint64_t)gridDim.x * blockDim.x) {
         if (i < n_out) {
             const uint64_t key = Tout[i];
             if (key == kEmpty64) continue;
-            atomicAdd(&sig_out[key_vertex(key)], (unsigned long long)sig_term_out(srcvert[key_source(key)]));
+            const int32_t v = key_vertex(key);
+            atomicAdd(&sig_out[v], (unsigned long long)sig_term_out(srcvert[key_source(key)]));
+            if (firstB && firstB[v] == (int32_t)key_source(key)) atomicMin(&fin[v], (int32_t)key_source(key));
         } else {
             const uint64_t key = Tin[i - n_out];
             if (key == kEmpty64) continue;
             if (clear_in) Tin[i - n_out] = kEmpty64;
             const int32_t v = key_vertex(key);
             atomicAdd(&sig_in[v], (unsigned long long)sig_term_in(srcvert[key_source(key)]));
-            if (table_contains(Tout, mout, limit, key)) atomicMin(&fin[v], (int32_t)key_source(key));
+            if ((firstF && firstF[v] == (int32_t)key_source(key)) || table_contains(Tout, mout, limit, key))
+                atomicMin(&fin[v], (int32_t)key_source(key));
         }
     }
 }
@@ -1288,15 +1370,29 @@ __global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, ui
 // by k_accumulate.
 __global__ void k_relabel_dense(int32_t n, uint64_t *Tout, uint64_t mout, const int32_t *srcvert,
                                 unsigned long long *sig_out, unsigned long long *sig_in, int32_t *fin, int32_t *label,
-                                CountStripes *cs) {
+                                CountStripes *cs, int32_t *firstF, int32_t *firstB) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= mout; i += stride) Tout[i] = kEmpty64;
     uint32_t cnt = 0;
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < (uint64_t)n; v += stride) {
         const int32_t l = label[v];
         if (l < 0) continue;
-        const int32_t f = fin[v];
-        const unsigned long long si = sig_in[v], so = sig_out[v];
+        int32_t f = fin[v];
+        unsigned long long si = sig_in[v], so = sig_out[v];
+        if (firstF) {
+            // the first-source slots: their pairs join the signatures, a
+            // source in both slots finishes the vertex, and the slots empty
+            const int32_t a = firstF[v], b = firstB[v];
+            if (a >= 0) {
+                so += sig_term_out(srcvert[a]);
+                firstF[v] = -1;
+            }
+            if (b >= 0) {
+                si += sig_term_in(srcvert[b]);
+                firstB[v] = -1;
+            }
+            if (a >= 0 && a == b && a < f) f = a;
+        }
         if (f != kInf32) {
             label[v] = ~srcvert[f];
             cnt++;
@@ -1369,8 +1465,11 @@ __global__ void k_canon_write(int32_t n, const int32_t *label, const int32_t *au
 }
 
 // ---------------------------------------------------------- reach output ----
-__global__ void k_emit_single(int32_t n, const int32_t *label, int32_t L, const uint32_t *vis, int32_t s,
-                              int32_t *pairs, uint64_t cap, Shared *sh) {
+// The pairs of a search as sort keys (j << vbits) | v, so that an ascending
+// sort orders them by (source index, vertex).  Slots come from one block
+// reservation each; keys past `cap` are counted but not written.
+__global__ void k_emit_single(int32_t n, const int32_t *label, int32_t L, const uint32_t *vis, uint64_t *keys,
+                              uint64_t cap, Shared *sh) {
     for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = v0 + threadIdx.x;
         const bool hit = v < n && label[v] == L && ((vis[v >> 5] >> (v & 31)) & 1u);
@@ -1378,16 +1477,13 @@ __global__ void k_emit_single(int32_t n, const int32_t *label, int32_t L, const 
         const uint32_t base = block_reserve(&sh->emit, (uint32_t)popc64(m));
         if (hit) {
             const uint64_t pos = (uint64_t)base + rank_below(m);
-            if (pos < cap) {
-                pairs[2 * pos] = (int32_t)v;
-                pairs[2 * pos + 1] = 0;
-            }
+            if (pos < cap) keys[pos] = (uint64_t)v;
         }
     }
-    (void)s;
 }
 
-__global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, uint64_t cap, Shared *sh) {
+__global__ void k_emit_table(const uint64_t *T, uint64_t mask, uint32_t vbits, uint64_t *keys, uint64_t cap,
+                             Shared *sh) {
     const uint64_t nt = mask + 1;
     for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x; i0 < nt; i0 += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t i = i0 + threadIdx.x;
@@ -1397,12 +1493,156 @@ __global__ void k_emit_table(const uint64_t *T, uint64_t mask, int32_t *pairs, u
         const uint32_t base = block_reserve(&sh->emit, (uint32_t)popc64(m));
         if (hit) {
             const uint64_t pos = (uint64_t)base + rank_below(m);
-            if (pos < cap) {
-                pairs[2 * pos] = key_vertex(key);
-                pairs[2 * pos + 1] = (int32_t)key_source(key);
+            if (pos < cap) keys[pos] = ((uint64_t)key_source(key) << vbits) | (uint64_t)(uint32_t)key_vertex(key);
+        }
+    }
+}
+
+// Sorted keys -> output pairs (vertex, source index).
+__global__ void k_unpack_pairs(const uint64_t *keys, uint64_t cnt, uint32_t vbits, int32_t *pairs) {
+    const uint64_t vmask = (1ull << vbits) - 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        pairs[2 * i] = (int32_t)(k & vmask);
+        pairs[2 * i + 1] = (int32_t)(k >> vbits);
+    }
+}
+
+// ------------------------------------------------------- connectivity ----
+// Connected components by LDD-UF-JTB (Algorithm 4): a low-diameter
+// decomposition grows clusters from randomly ordered centres added in
+// batches of growing size, each round searching out from the frontier
+// (Section 5.1 runs these searches with VGC and the hash bag); every vertex
+// ends with owner[v], the centre of its cluster.  A union-find over the arcs
+// whose endpoints have different owners then merges clusters.
+
+// Adds batch [p0, p1) of the centre order to the frontier: a vertex not yet
+// claimed by any cluster becomes a centre (its own owner) and a frontier
+// entry (v, v).  The frontier grows at rc->nF[par]; its degree sum too.
+__global__ __launch_bounds__(kBlock) void k_ldd_add(Perm P, uint32_t p0, uint32_t p1, const int32_t *off, uint32_t *vis,
+                                                    int32_t *owner, uint64_t *F, uint64_t fcap, RoundCtl *rc, int par) {
+    __shared__ unsigned long long dpart[kWavesPerBlock];
+    unsigned long long deg = 0;
+    for (uint64_t j0 = p0 + (uint64_t)blockIdx.x * blockDim.x; j0 < p1; j0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t j = j0 + threadIdx.x;
+        bool mine = false;
+        int32_t v = 0;
+        if (j < p1) {
+            v = (int32_t)perm_apply(P, (uint32_t)j);
+            mine = claim_bit(vis, v);
+        }
+        const uint64_t m = ballot(mine);
+        const uint32_t base = block_reserve(&rc->nF[par], (uint32_t)popc64(m));
+        if (mine) {
+            owner[v] = v;
+            const uint64_t pos = (uint64_t)base + rank_below(m);
+            if (pos < fcap) F[pos] = pair_key(v, (uint32_t)v);
+            else atomicOr(&rc->err, kErrCapacity);
+            deg += (unsigned long long)(off[v + 1] - off[v]);
+        }
+    }
+    deg = wave_sum_u64(deg);
+    if (lane_id() == 0) dpart[threadIdx.x / kWave] = deg;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kWavesPerBlock; w++) t += dpart[w];
+        if (t) atomicAdd(&rc->fdeg[par], t);
+    }
+}
+
+// Union-find with randomized linking (the root of lower priority is linked
+// under the other; priority = a hash of the id, ties by id) and path
+// splitting in find (Jayanti, Tarjan and Boix-Adsera's concurrent
+// union-find, the "UF-JTB" of Algorithm 4).
+__device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x) {
+    for (;;) {
+        const int32_t p = (int32_t)ld_relaxed(reinterpret_cast<const uint32_t *>(parent + x));
+        if (p == x) return x;
+        const int32_t g = (int32_t)ld_relaxed(reinterpret_cast<const uint32_t *>(parent + p));
+        if (g == p) return p;
+        // x's parent moves up to its grandparent (still an ancestor of x)
+        __hip_atomic_store(parent + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = g;
+    }
+}
+
+__device__ __forceinline__ bool uf_higher(int32_t a, int32_t b) {
+    const uint64_t ha = mix64((uint64_t)(uint32_t)a ^ 0x7F4A7C15ull), hb = mix64((uint64_t)(uint32_t)b ^ 0x7F4A7C15ull);
+    return ha != hb ? ha > hb : a > b;
+}
+
+__device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) {
+    for (;;) {
+        a = uf_find(parent, a);
+        b = uf_find(parent, b);
+        if (a == b) return;
+        if (uf_higher(b, a)) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        // b (the lower priority root) goes under a, unless b stopped being a root
+        if (atomicCAS(parent + b, b, a) == b) return;
+    }
+}
+
+// bstart[b] = the vertex whose adjacency holds arc b * A (the arc blocks of
+// k_cc_union start from it).
+__global__ void k_arc_block_starts(int32_t n, const int32_t *off, int64_t A, int32_t *bstart) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lo = off[u], hi = off[u + 1];
+        for (int64_t b = (lo + A - 1) / A; b * A < hi; b++) bstart[b] = (int32_t)u;
+    }
+}
+
+// The union pass: block b owns arcs [b A, (b + 1) A), thread t the run of
+// A / kBlock arcs at b A + t A / kBlock; its first arc's vertex is found by a
+// binary search between the vertices that start this block and the next.
+constexpr int64_t kUnionArcs = 4096;
+__global__ __launch_bounds__(kBlock) void k_cc_union(int32_t n, int64_t m, const int32_t *off, const int32_t *adj,
+                                                     const int32_t *owner, int32_t *parent, const int32_t *bstart,
+                                                     Counters *cn) {
+    constexpr int64_t per = kUnionArcs / kBlock;
+    const int64_t nb = (m + kUnionArcs - 1) / kUnionArcs;
+    unsigned long long c_arcs = 0, c_unions = 0;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t e0 = b * kUnionArcs + (int64_t)threadIdx.x * per;
+        if (e0 >= m) continue;
+        int32_t lo = bstart[b], hi = b + 1 < nb ? bstart[b + 1] : n - 1;
+        while (lo < hi) {  // the largest u with off[u] <= e0
+            const int32_t mid = lo + (hi - lo + 1) / 2;
+            if (off[mid] <= e0) lo = mid; else hi = mid - 1;
+        }
+        int32_t u = lo;
+        int32_t ou = owner[u];
+        int64_t next = off[u + 1];
+        const int64_t e1 = e0 + per < m ? e0 + per : m;
+        for (int64_t e = e0; e < e1; e++) {
+            if (e >= next) {
+                do {
+                    u++;
+                    next = off[u + 1];
+                } while (e >= next);
+                ou = owner[u];
+            }
+            const int32_t ow = owner[adj[e]];
+            c_arcs++;
+            if (ow != ou) {
+                c_unions++;
+                uf_union(parent, ou, ow);
             }
         }
     }
+    unsigned long long c[kNumCtr] = {0, 0, c_arcs, c_unions, 0, 0};
+    block_flush_ctr(cn->c[blockIdx.x % kCtrStripes][kKindPull], c);
+}
+
+// Final component of every vertex as a finished SCC-style key (~root), so
+// that the canonical-minimum kernels turn it into the component's smallest id.
+__global__ void k_cc_finish(int32_t n, const int32_t *owner, int32_t *parent, int32_t *label) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        label[v] = ~uf_find(parent, owner[v]);
 }
 
 // ------------------------------------------------------------ bag test ----

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -19,6 +20,8 @@
 #include <string>
 #include <utility>
 #include <vector>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "hipscc.h"
 #include "kernels.h"
@@ -67,7 +70,7 @@ struct scc_ctx {
     int num_cu = 256;
     uint64_t table_slots_max = 1ull << 24;  // cap of the estimated reach-table size (set from device memory)
     int expand_blocks = 2048;
-    int expand_grid[2][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
+    int expand_grid[4][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
     int arcs_per_lane = 1;          // options.arcs_per_lane of the current call
     double vgc_fill = 2.0;          // options.vgc_fill of the current call
     std::string err;
@@ -78,14 +81,19 @@ struct scc_ctx {
     DevBuf<uint32_t> vis[2];        // visited bitmaps of the two single-source lanes
     DevBuf<uint32_t> bm[2][2];      // front/next bitmaps per lane (dense mode)
     DevBuf<uint64_t> Tout, Tin;     // reach tables (forward, backward)
+    DevBuf<int32_t> firstS[2];      // first-source slots per direction (options.first_slot)
+    int64_t first_clean_n = 0;      // the slots are known empty (-1) on [0, first_clean_n)
     DevBuf<uint64_t> F[2], heavy[2];
     DevBuf<uint64_t> bag_slots[2];
     DevBuf<uint32_t> bag_cnt[2];
     uint32_t bag_nchunks[2] = {0, 0};
-    uint32_t bag_lam_log2 = 0;
+    uint32_t bag_lam_log2[2] = {0, 0};  // each lane's first-chunk size (log2)
     DevCtl *dctl = nullptr;
     DevCtl *hctl = nullptr;         // pinned
     DevBuf<int32_t> ubuf;           // batched: union CSR scratch
+    DevBuf<uint64_t> rkeys[2];      // scc_reach: pair sort keys (double buffer)
+    DevBuf<uint8_t> rtemp;          // scc_reach: radix sort scratch
+    DevBuf<int32_t> bstart;         // scc_cc: first vertex of each arc block
     uint32_t salt = 1;
     bool tables_dirty = false;      // a failed call may leave claims behind
     // stamp/fin/sig_in/sig_out are known clean on [0, vclean_n) (zero sums,
@@ -112,6 +120,11 @@ struct scc_ctx {
     size_t pev_used = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> plog;
     Policy policy;
+    // statistics of the last scc_bag_selftest: (round, chunk, load, cause) for
+    // every chunk left before its round's ExtractAll, and each round's used
+    // prefix
+    std::vector<double> bag_rows;
+    std::vector<int64_t> bag_prefix;
 };
 
 namespace {
@@ -254,7 +267,7 @@ scc_options_t defaults() {
     o.table_floor = 1.2f;
     o.lambda_log2 = 0;
     o.sigma = 50;
-    o.kappa = 8;
+    o.kappa = 32;
     o.alpha = 0.5f;
     o.seed = 0x5EEDull;
     o.policy = 0;
@@ -264,6 +277,7 @@ scc_options_t defaults() {
     o.table_init = 0;
     o.seeds_per_wave = 0;
     o.timing = 0;
+    o.ldd_beta = 1.2f;
     return o;
 }
 
@@ -309,6 +323,10 @@ void check_opts(scc_ctx *c, const scc_options_t &o) {
     }
     if (o.policy < 0 || o.policy > 2) { set_err(c, "policy must be 0, 1 or 2"); throw Fail{SCC_EINVAL}; }
     if (o.dense < -1 || o.dense > 1) { set_err(c, "dense must be -1, 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (o.union_arcs_max < 0) { set_err(c, "union_arcs_max must be >= 0"); throw Fail{SCC_EINVAL}; }
+    if (o.first_slot < 0 || o.first_slot > 1) { set_err(c, "first_slot must be 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (o.vgc_measure < 0 || o.vgc_measure > 1) { set_err(c, "vgc_measure must be 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (!(o.ldd_beta > 1.0f) || !(o.ldd_beta < 1e6f)) { set_err(c, "ldd_beta must be > 1"); throw Fail{SCC_EINVAL}; }
 }
 
 // Buffers of lane `id` sized for up to `entries` frontier entries per round.
@@ -324,9 +342,12 @@ void ensure_lane(scc_ctx *c, int id, uint64_t entries, uint32_t lam_log2) {
     bool g2 = false;
     ensure(c, c->bag_slots[id], cap);
     ensure(c, c->bag_cnt[id], cap >> kStripeLog2, &g2);
-    if (g2 || lam_log2 != c->bag_lam_log2) fill_u32(c, c->bag_cnt[id].p, c->bag_cnt[id].cap, 0u);
-    if (nch > c->bag_nchunks[id] || lam_log2 != c->bag_lam_log2) c->bag_nchunks[id] = nch;
-    c->bag_lam_log2 = lam_log2;
+    // the chunk count belongs to the lane's own lambda: it is recomputed
+    // whenever that lambda changes, and only grows while it stays
+    const bool lam_changed = lam_log2 != c->bag_lam_log2[id];
+    if (g2 || lam_changed) fill_u32(c, c->bag_cnt[id].p, c->bag_cnt[id].cap, 0u);
+    if (nch > c->bag_nchunks[id] || lam_changed) c->bag_nchunks[id] = nch;
+    c->bag_lam_log2[id] = lam_log2;
     ensure(c, c->F[id], entries + kWave);
     ensure(c, c->heavy[id], 2 * (entries + kWave));
 }
@@ -347,20 +368,30 @@ Search make_search(scc_ctx *c, int id, const scc_options_t &o, int mode) {
     S.bag.slots = c->bag_slots[id].p;
     S.bag.cnt = c->bag_cnt[id].p;
     S.bag.ctl = &c->dctl->bag[id];
-    S.bag.lam_log2 = c->bag_lam_log2;
+    S.bag.lam_log2 = c->bag_lam_log2[id];
     S.bag.nchunks = c->bag_nchunks[id];
+    // every chunk the kernels may use lies inside the lane's slot and
+    // stripe-counter buffers
+    const uint64_t used = (1ull << S.bag.lam_log2) << (S.bag.nchunks ? S.bag.nchunks - 1 : 0);
+    if (S.bag.nchunks < 1 || S.bag.nchunks > (uint32_t)kMaxChunks || used > c->bag_slots[id].cap ||
+        (used >> kStripeLog2) > c->bag_cnt[id].cap) {
+        set_err(c, "internal: hash bag of lane %d (lambda 2^%u, %u chunks) exceeds its buffers", id,
+                S.bag.lam_log2, S.bag.nchunks);
+        throw Fail{SCC_EINTERNAL};
+    }
     S.bag.sigma = (uint32_t)o.sigma;
     S.bag.kappa = (uint32_t)o.kappa;
     S.bag.alpha = o.alpha;
     S.rc = &c->dctl->lane[id];
     S.ls = &c->dctl->ls[id];
     S.cn = &c->dctl->cn;
-    S.kind = mode == kMulti ? kKindExpandMulti : kKindExpandSingle;
+    S.kind = (mode == kMulti || mode == kMultiFirst) ? kKindExpandMulti : kKindExpandSingle;
     S.tau = o.tau;
     S.seeds = o.seeds_per_wave;
     S.heavy_deg = 1024;
     S.probe_limit = kProbeLimit;
     S.vgc_cut = (uint32_t)c->expand_blocks * kWavesPerBlock;
+    S.measure = o.vgc_measure;
     return S;
 }
 
@@ -466,6 +497,16 @@ void timed_collect(scc_ctx *c) {
 
 // The expand kernel of a search mode and arcs-per-lane setting.
 const void *expand_kernel(int mode, int apl) {
+    if (mode == kLdd) {
+        if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kLdd, 1>);
+        if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kLdd, 2>);
+        return reinterpret_cast<const void *>(&k_expand<kLdd, 4>);
+    }
+    if (mode == kMultiFirst) {
+        if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kMultiFirst, 1>);
+        if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kMultiFirst, 2>);
+        return reinterpret_cast<const void *>(&k_expand<kMultiFirst, 4>);
+    }
     if (mode == kMulti) {
         if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kMulti, 1>);
         if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kMulti, 2>);
@@ -507,8 +548,11 @@ void launch_sparse(scc_ctx *c, Lane **ls, int nl) {
     HIPCHK(hipLaunchKernel(fn, dim3(eb), dim3(kBlock), args, 0, c->stream));
     timed_end(c, t);
     P.split = hb / 2;
-    const int th = timed_begin(c, mode == kMulti ? SCC_KERNEL_HEAVY_MULTI : SCC_KERNEL_HEAVY_SINGLE);
-    if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    const bool pairs = mode == kMulti || mode == kMultiFirst;
+    const int th = timed_begin(c, pairs ? SCC_KERNEL_HEAVY_MULTI : SCC_KERNEL_HEAVY_SINGLE);
+    if (mode == kLdd) hipLaunchKernelGGL(k_expand_heavy<kLdd>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    else if (mode == kMultiFirst) hipLaunchKernelGGL(k_expand_heavy<kMultiFirst>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    else if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     LAUNCHCHK("k_expand_heavy");
     timed_end(c, th);
@@ -554,19 +598,23 @@ void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
     bool grew = false;
     ensure(c, *L.T, ts, &grew);
     fill_u64(c, L.T->p, grew ? L.T->cap : ts, kEmpty64);
-    ensure_lane(c, L.id, std::max<uint64_t>(ts, (uint64_t)P.n), c->bag_lam_log2);
+    ensure_lane(c, L.id, std::max<uint64_t>(ts, (uint64_t)P.n), c->bag_lam_log2[L.id]);
     reset_bag(c, L.id);
     reset_lane_ctl(c, L.id);
-    Search S = make_search(c, L.id, *P.o, kMulti);
+    Search S = make_search(c, L.id, *P.o, L.mode);
     S.off = L.S.off;
     S.adj = L.S.adj;
     S.label = L.S.label;
     S.srclab = L.S.srclab;
+    S.first = L.S.first;
     S.table = L.T->p;
     S.tmask = ts - 1;
     L.S = S;
+    // the abandoned attempt's first-source claims go too
+    if (S.first) fill_u32(c, (uint32_t *)S.first, (uint64_t)P.n, 0xffffffffu);
     SeedArgs A;
     memset(&A, 0, sizeof A);
+    A.first[0] = S.first;
     A.T[0] = S.table;
     A.mask[0] = S.tmask;
     A.F[0] = S.F;
@@ -620,12 +668,12 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
     // frontier is a few microseconds of empty launches); single-source
     // searches start at 1 so that the dense switch is seen in time.
     bool all_multi = true;
-    for (int i = 0; i < nl; i++) all_multi = all_multi && lanes[i].mode == kMulti;
+    for (int i = 0; i < nl; i++) all_multi = all_multi && lanes[i].mode != kSingle;
     int K = all_multi ? 2 : 1;
     uint64_t launched = 0;
     uint64_t limit = (uint64_t)P.n + 64;
     for (int i = 0; i < nl; i++)
-        if (lanes[i].mode == kMulti) limit = std::max<uint64_t>(limit, 2 * *lanes[i].tslots + 64);
+        if (lanes[i].mode != kSingle) limit = std::max<uint64_t>(limit, 2 * *lanes[i].tslots + 64);
     bool was_dense[2] = {false, false};
     for (;;) {
         bool any = false, watch = false;
@@ -687,7 +735,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
             if (!L.live) continue;
             const RoundCtl &rc = c->hctl->lane[L.id];
             const bool lane_full = (rc.err & kErrCapacity) || c->hctl->bag[L.id].overflow;
-            if (lane_full && L.mode != kMulti) {
+            if (lane_full && L.mode == kSingle) {
                 // a single-source frontier holds each vertex at most once
                 set_err(c, "frontier capacity exceeded (err=%u, bag overflow=%u)", rc.err, c->hctl->bag[L.id].overflow);
                 throw Fail{SCC_EINTERNAL};
@@ -701,14 +749,17 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
                                              (float)L.nsub, (float)rc.snap_rounds, (float)rc.snap_depth, x);
                 const float tau = (float)(use_policy ? rc.tau_cur : (uint32_t)std::max(L.S.tau, 0));
                 const float row[SCC_TRACE_FIELDS] = {
-                    (float)(L.mode == kMulti ? 2 : (was_dense[L.id] ? 1 : 0)), x[0], x[1], x[2], x[3], x[4], tau, ms,
+                    (float)(L.mode != kSingle ? 2 : (was_dense[L.id] ? 1 : 0)), x[0], x[1], x[2], x[3], x[4], tau, ms,
                     (float)(rc.claims - rc.snap_claims), (float)nf_new, (float)c->epoch, (float)P.n};
                 c->trace.insert(c->trace.end(), row, row + SCC_TRACE_FIELDS);
             }
             // a multi-source search whose reach table or frontier buffers ran
             // out restarts with both doubled
-            if (L.mode == kMulti && ((rc.err & kErrTable) || lane_full)) {
-                if (P.st) P.st->rounds_multi += rc.rounds;  // rounds of the abandoned attempt
+            if (L.mode != kSingle && ((rc.err & kErrTable) || lane_full)) {
+                if (P.st) {
+                    P.st->rounds_multi += rc.rounds;  // rounds of the abandoned attempt
+                    P.st->restart_rounds += rc.rounds;
+                }
                 restart_multi(c, L, P);
                 L.fdeg = L.claims = 0;
                 L.rounds = 0;
@@ -969,6 +1020,21 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         ensure_lane(c, i, (uint64_t)n, lam_log2_for(o, (uint64_t)n));
         reset_bag(c, i);
     }
+    // first-source slots: empty unless the previous call left them so
+    const bool use_first = o.first_slot == 1;
+    int64_t first_clean_after = c->first_clean_n;
+    if (use_first) {
+        for (int d = 0; d < 2; d++) {
+            bool grew = false;
+            ensure(c, c->firstS[d], (uint64_t)n, &grew);
+            if (grew) c->first_clean_n = 0;
+        }
+        if (c->first_clean_n < n) {
+            for (int d = 0; d < 2; d++) fill_u32(c, (uint32_t *)c->firstS[d].p, (uint64_t)n, 0xffffffffu);
+            first_clean_after = n;
+        }
+        c->first_clean_n = 0;  // until this call ends normally
+    }
     phase_end(c, ph);
 
     // ---- trimming (Section 4.1) and the random permutation (Algorithm 1)
@@ -1112,7 +1178,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             // frontier buffers for one round's pairs: up to 2n (a search that
             // needs more restarts with larger ones)
             ensure_lane(c, d, std::max<uint64_t>(std::min<uint64_t>(d ? ts_in : ts_out, 2 * (uint64_t)n), (uint64_t)n),
-                        c->bag_lam_log2);
+                        c->bag_lam_log2[d]);
         resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_rs).count();
         SeedArgs SA;
         memset(&SA, 0, sizeof SA);
@@ -1121,11 +1187,13 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             uint64_t &ts = d ? ts_in : ts_out;
             L[d] = Lane();
             L[d].id = d;
-            L[d].mode = kMulti;
+            L[d].mode = use_first ? kMultiFirst : kMulti;
             L[d].n = n;
             L[d].T = &T;
             L[d].tslots = &ts;
-            L[d].S = make_search(c, d, o, kMulti);
+            L[d].S = make_search(c, d, o, L[d].mode);
+            L[d].S.first = use_first ? c->firstS[d].p : nullptr;
+            SA.first[d] = L[d].S.first;
             L[d].S.off = d ? g.in_off : g.out_off;
             L[d].S.adj = d ? g.in_adj : g.out_adj;
             L[d].S.label = c->label.p;
@@ -1167,15 +1235,18 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         const uint64_t tot = ts_out + ts_in;
         // a batch with many pairs relabels per vertex (one coalesced pass),
         // a small one per table slot (random accesses to the touched vertices)
-        const bool dense_label = (a_out + a_in) * kDenseLabelDiv >= (uint64_t)n;
+        // (first-source slots are read per vertex, so such batches always
+        // take the per-vertex relabel)
+        const bool dense_label = use_first || (a_out + a_in) * kDenseLabelDiv >= (uint64_t)n;
+        int32_t *fF = use_first ? c->firstS[0].p : nullptr, *fB = use_first ? c->firstS[1].p : nullptr;
         hipLaunchKernelGGL(k_accumulate, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
                            c->Tin.p, ts_in - 1, kProbeLimit, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p,
-                           dense_label);
+                           dense_label, fF, fB);
         LAUNCHCHK("k_accumulate");
         if (dense_label) {
             hipLaunchKernelGGL(k_relabel_dense, dim3(grid_for(c, std::max<uint64_t>(ts_out, (uint64_t)n))), dim3(kBlock),
                                0, c->stream, n, c->Tout.p, ts_out - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p,
-                               c->fin.p, c->label.p, &c->dctl->cs);
+                               c->fin.p, c->label.p, &c->dctl->cs, fF, fB);
             LAUNCHCHK("k_relabel_dense");
         } else {
             hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p,
@@ -1220,6 +1291,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     }
     c->tables_dirty = false;
     c->vclean_n = clean_after;
+    if (use_first) c->first_clean_n = first_clean_after;
 }
 
 // sources check for scc_reach: in range, label >= 0, distinct (stamp epoch)
@@ -1326,6 +1398,7 @@ void accumulate_stats(scc_stats_t &acc, const scc_stats_t &st) {
     acc.bag_inserts += st.bag_inserts;
     acc.bag_chunk_advances += st.bag_chunk_advances;
     acc.table_restarts += st.table_restarts;
+    acc.restart_rounds += st.restart_rounds;
     acc.trimmed += st.trimmed;
     acc.n_scc += st.n_scc;
     acc.policy_calls += st.policy_calls;
@@ -1382,7 +1455,7 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
         // one resident wave of blocks per expand variant: its waves take the
         // frontier's groups statically, so blocks beyond the resident set
         // would run a second, serial local search
-        for (int m = 0; m < 2; m++)
+        for (int m = 0; m < 4; m++)
             for (int ai = 0; ai < 3; ai++) {
                 int b = 0;
                 HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, expand_kernel(m, 1 << ai), kBlock, 0));
@@ -1418,6 +1491,8 @@ void scc_destroy(scc_ctx_t *c) {
         release(c->F[i]); release(c->heavy[i]); release(c->bag_slots[i]); release(c->bag_cnt[i]);
     }
     release(c->Tout); release(c->Tin); release(c->ubuf);
+    release(c->firstS[0]); release(c->firstS[1]);
+    release(c->rkeys[0]); release(c->rkeys[1]); release(c->rtemp); release(c->bstart);
     policy_release(c->policy);
     if (c->dctl) (void)hipFree(c->dctl);
     if (c->hctl) (void)hipHostFree(c->hctl);
@@ -1499,6 +1574,11 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
         L.id = 0;
         L.n = n;
         uint64_t ts = 0;
+        // sort keys (j << vbits) | v: vbits covers the vertex ids, kbits the
+        // source indices
+        uint32_t vbits = 1, kbits = 0;
+        while ((1ll << vbits) < (int64_t)n) vbits++;
+        while ((1ll << kbits) < (int64_t)k) kbits++;
         if (k == 1) {
             int32_t s = 0, lab = 0;
             HIPCHK(hipMemcpyAsync(&s, sources, 4, hipMemcpyDeviceToHost, c->stream));
@@ -1523,8 +1603,9 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
             L.radj = dir ? g->out_adj : g->in_adj;
             drive(c, &L, 1, DP);
             fill_u32(c, &sh->emit, 1, 0u);
+            ensure(c, c->rkeys[0], (uint64_t)n);
             hipLaunchKernelGGL(k_emit_single, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, labels, lab,
-                               c->vis[0].p, s, pairs_out, (uint64_t)capacity, sh);
+                               c->vis[0].p, c->rkeys[0].p, c->rkeys[0].cap, sh);
             LAUNCHCHK("k_emit_single");
         } else {
             ts = next_pow2(std::max<uint64_t>(std::max<uint64_t>(1024, 4ull * (uint64_t)k),
@@ -1557,8 +1638,9 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
             L.S.tmask = ts - 1;
             drive(c, &L, 1, DP);
             fill_u32(c, &sh->emit, 1, 0u);
+            ensure(c, c->rkeys[0], ts);
             hipLaunchKernelGGL(k_emit_table, dim3(grid_for(c, ts)), dim3(kBlock), 0, c->stream, c->Tout.p, ts - 1,
-                               pairs_out, (uint64_t)capacity, sh);
+                               vbits, c->rkeys[0].p, c->rkeys[0].cap, sh);
             LAUNCHCHK("k_emit_table");
             // leave the table clean for the next call
             fill_u64(c, c->Tout.p, ts, kEmpty64);
@@ -1566,6 +1648,25 @@ scc_status scc_reach(scc_ctx_t *c, const scc_graph_t *g, int32_t dir, const int3
         sync_ctl(c, stats != nullptr);
         c->tables_dirty = false;
         *n_pairs = (int64_t)c->hctl->sh.emit;
+        if (*n_pairs > (int64_t)c->rkeys[0].cap) {
+            set_err(c, "internal: %lld pairs exceed the key buffer", (long long)*n_pairs);
+            throw Fail{SCC_EINTERNAL};
+        }
+        if (*n_pairs > 0 && *n_pairs <= capacity) {
+            // ascending (source index, vertex) order, sorted on the device
+            const uint64_t cnt = (uint64_t)*n_pairs;
+            ensure(c, c->rkeys[1], cnt);
+            size_t tb = 0;
+            HIPCHK(rocprim::radix_sort_keys(nullptr, tb, c->rkeys[0].p, c->rkeys[1].p, cnt, 0u, vbits + kbits,
+                                            c->stream));
+            ensure(c, c->rtemp, (uint64_t)tb);
+            HIPCHK(rocprim::radix_sort_keys((void *)c->rtemp.p, tb, c->rkeys[0].p, c->rkeys[1].p, cnt, 0u,
+                                            vbits + kbits, c->stream));
+            hipLaunchKernelGGL(k_unpack_pairs, dim3(grid_for(c, cnt)), dim3(kBlock), 0, c->stream, c->rkeys[1].p, cnt,
+                               vbits, pairs_out);
+            LAUNCHCHK("k_unpack_pairs");
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
         if (stats) {
             stats->ms_total = now_ms() - t0;
             if (k == 1) stats->rounds_first = L.rounds; else stats->rounds_multi = L.rounds;
@@ -1621,7 +1722,7 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
         scc_stats_t acc;
         memset(&acc, 0, sizeof acc);
         int32_t g0 = 0;
-        const int64_t lim = (1ll << 31) - 1;
+        const int64_t lim = o.union_arcs_max > 0 ? (int64_t)o.union_arcs_max : (1ll << 31) - 1;
         while (g0 < G) {
             int32_t g1 = g0 + 1;
             while (g1 < G && arc_base[g1 + 1] - arc_base[g0] < lim) g1++;
@@ -1658,6 +1759,133 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
             acc.m = arc_base[G];
             acc.ms_total = now_ms() - t0;
             *stats = acc;
+        }
+    });
+}
+
+scc_status scc_cc(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, const scc_options_t *opt,
+                  scc_stats_t *stats) {
+    return guard(c, [&] {
+        if (!g) { set_err(c, "graph is NULL"); throw Fail{SCC_EINVAL}; }
+        if (g->n < 0 || g->m < 0) { set_err(c, "negative n or m"); throw Fail{SCC_EINVAL}; }
+        if (!g->out_off || (g->m > 0 && !g->out_adj)) { set_err(c, "graph has a NULL out array"); throw Fail{SCC_EINVAL}; }
+        if (g->n > 0 && !labels_out) { set_err(c, "labels_out is NULL"); throw Fail{SCC_EINVAL}; }
+        scc_options_t o = opt ? *opt : defaults();
+        check_opts(c, o);
+        const double t0 = now_ms();
+        init_call(c, stats, g->n, g->m, &o);
+        const int32_t n = g->n;
+        const int64_t m = g->m;
+        if (n == 0) return;
+        const bool ph = stats != nullptr;
+        ensure_vertex_state(c, n);
+        if (o.validate) {
+            uint32_t *bad = &c->dctl->sh.bad;
+            fill_u32(c, bad, 1, 0u);
+            hipLaunchKernelGGL(k_validate_off, dim3(grid_for(c, (uint64_t)n + 1)), dim3(kBlock), 0, c->stream, n,
+                               g->m, g->out_off, bad);
+            if (m > 0)
+                hipLaunchKernelGGL(k_validate_adj, dim3(grid_for(c, (uint64_t)m)), dim3(kBlock), 0, c->stream, n, g->m,
+                                   g->out_adj, (int32_t *)nullptr, bad);
+            LAUNCHCHK("k_validate_*");
+            sync_ctl(c);
+            if (c->hctl->sh.bad) { set_err(c, "invalid CSR (offsets or arc targets)"); throw Fail{SCC_EGRAPH}; }
+        }
+        int32_t *owner = c->srcvert.p, *parent = c->srclab.p;
+        // ---- low-diameter decomposition (Algorithm 4, LDD): one search
+        // lane, a centre batch added before every round
+        phase_begin(c, 1, ph);
+        ensure_lane(c, 0, (uint64_t)n, lam_log2_for(o, (uint64_t)n));
+        reset_bag(c, 0);
+        reset_lane_ctl(c, 0);
+        fill_u32(c, (uint32_t *)&c->dctl->ls[0], sizeof(LaneStripes) / 4, 0u);
+        fill_u32(c, c->vis[0].p, (uint64_t)n / 32 + 2, 0u);
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, parent);
+        LAUNCHCHK("k_iota");
+        Perm P;
+        P.n = (uint32_t)n;
+        uint32_t bits = 1;
+        while ((1ull << (2 * bits)) < (uint64_t)n) bits++;
+        P.half_bits = bits;
+        P.key = mix64(o.seed ^ 0x452821E638D01377ull);
+        Lane L;
+        L.id = 0;
+        L.mode = kLdd;
+        L.n = n;
+        L.S = make_search(c, 0, o, kLdd);
+        L.S.off = g->out_off;
+        L.S.adj = g->out_adj;
+        L.S.vis = c->vis[0].p;
+        L.S.owner = owner;
+        L.avg_deg = std::max(1.0, (double)m / (double)n);
+        L.par = 0;
+        uint64_t pos = 0;
+        double bsize = 1.0;
+        int64_t rounds = 0;
+        while (pos < (uint64_t)n) {
+            // every vertex of the batch that no cluster has reached yet
+            // becomes a centre (Algorithm 4 adds B_i to the frontier)
+            const uint64_t sz = std::max<uint64_t>((uint64_t)std::ceil(bsize - 1e-9), 1);
+            const uint64_t p1 = std::min<uint64_t>((uint64_t)n, pos + sz);
+            hipLaunchKernelGGL(k_ldd_add, dim3(grid_for(c, p1 - pos)), dim3(kBlock), 0, c->stream, P, (uint32_t)pos,
+                               (uint32_t)p1, g->out_off, c->vis[0].p, owner, L.S.F, L.S.fcap, L.S.rc, L.par);
+            LAUNCHCHK("k_ldd_add");
+            pos = p1;
+            bsize *= (double)o.ldd_beta;
+            // once every vertex has a cluster the remaining frontier could
+            // only find claimed vertices: the decomposition is complete
+            if (pos >= (uint64_t)n) break;
+            launch_sparse(c, std::array<Lane *, 1>{&L}.data(), 1);
+            rounds++;
+            if (rounds % kMaxSlots == 0) {
+                sync_ctl(c);
+                timed_collect(c);
+                if ((c->hctl->lane[0].err & kErrCapacity) || c->hctl->bag[0].overflow) {
+                    set_err(c, "internal: LDD frontier capacity exceeded");
+                    throw Fail{SCC_EINTERNAL};
+                }
+            }
+        }
+        sync_ctl(c);
+        timed_collect(c);
+        if ((c->hctl->lane[0].err & kErrCapacity) || c->hctl->bag[0].overflow) {
+            set_err(c, "internal: LDD frontier capacity exceeded");
+            throw Fail{SCC_EINTERNAL};
+        }
+        phase_end(c, ph);
+        // ---- union-find over the arcs between clusters, then the canonical
+        // smallest vertex id per component
+        phase_begin(c, 4, ph);
+        if (m > 0) {
+            const int64_t nb = (m + kUnionArcs - 1) / kUnionArcs;
+            ensure(c, c->bstart, (uint64_t)nb + 1);
+            hipLaunchKernelGGL(k_arc_block_starts, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n,
+                               g->out_off, (int64_t)kUnionArcs, c->bstart.p);
+            hipLaunchKernelGGL(k_cc_union, dim3((unsigned)std::min<int64_t>(nb, (int64_t)c->num_cu * 16)), dim3(kBlock),
+                               0, c->stream, n, m, g->out_off, g->out_adj, owner, parent, c->bstart.p, &c->dctl->cn);
+            LAUNCHCHK("k_cc_union");
+        }
+        hipLaunchKernelGGL(k_cc_finish, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, owner, parent,
+                           c->label.p);
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->aux.p);
+        hipLaunchKernelGGL(k_canon_min, dim3(grid_for(c, (uint64_t)n, 4)), dim3(kBlock), 0, c->stream, n, c->label.p,
+                           c->aux.p, &c->dctl->sh.bad);
+        hipLaunchKernelGGL(k_canon_write, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, c->label.p,
+                           c->aux.p, labels_out, &c->dctl->cs);
+        LAUNCHCHK("k_cc_finish / canonical");
+        phase_end(c, ph);
+        sync_ctl(c, stats != nullptr);
+        if (c->hctl->sh.bad & kErrUnfinished) { set_err(c, "internal: a vertex ended without a component"); throw Fail{SCC_EINTERNAL}; }
+        if (stats) {
+            double ms[kPhases] = {0, 0, 0, 0, 0};
+            phase_collect(c, ms);
+            stats->ms_first = ms[1];
+            stats->ms_label = ms[4];
+            stats->rounds_first = rounds;
+            stats->batches = rounds + 1;
+            stats->n_scc = count_sum(c, &CountLine::nscc);
+            fill_counters(c, stats, n);
+            stats->ms_total = now_ms() - t0;
         }
     });
 }
@@ -1709,9 +1937,14 @@ scc_status scc_bag_selftest(scc_ctx_t *c, const uint64_t *keys, int64_t n, int32
         ensure(c, c->F[0], (uint64_t)n + kWave);
         reset_bag(c, 0);
         Search S = make_search(c, 0, o, kSingle);
+        S.bag.track = 1;
+        c->bag_rows.clear();
+        c->bag_prefix.clear();
         uint64_t adv = 0;
         for (int32_t rr = 0; rr < rounds; rr++) {
             S.bag.salt = c->salt++;
+            fill_u32(c, c->dctl->bag[0].fill, kMaxChunks, 0u);
+            fill_u32(c, (uint32_t *)&c->dctl->bag[0].forced, 2, 0u);
             hipLaunchKernelGGL(k_bag_insert_test, dim3((unsigned)c->num_cu * 4), dim3(kBlock), 0, c->stream, keys, n,
                                rounds, rr, S.bag, S.cn);
             LAUNCHCHK("k_bag_insert_test");
@@ -1727,6 +1960,18 @@ scc_status scc_bag_selftest(scc_ctx_t *c, const uint64_t *keys, int64_t n, int32
             hipLaunchKernelGGL(k_bag_extract, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, LP);
             LAUNCHCHK("k_bag_extract");
             fill_u32(c, &c->dctl->bag[0].advances, 1, 0u);
+            // chunks below the one current at ExtractAll were left during the
+            // round: their fill is the load at the move (plus late inserts)
+            sync_ctl(c);
+            const BagCtl &bc = c->hctl->bag[0];
+            for (uint32_t i = 0; i < bc.last_r && i < (uint32_t)kMaxChunks; i++) {
+                const double size = (double)(bag_chunk_hi(S.bag, i) - bag_chunk_lo(S.bag, i));
+                c->bag_rows.push_back((double)rr);
+                c->bag_rows.push_back((double)i);
+                c->bag_rows.push_back((double)bc.fill[i] / size);
+                c->bag_rows.push_back((double)((bc.forced >> i) & 1ull));
+            }
+            c->bag_prefix.push_back((int64_t)bag_chunk_hi(S.bag, bc.last_r));
         }
         sync_ctl(c, true);
         const uint64_t got = c->hctl->lane[0].nF[0];
@@ -1739,6 +1984,22 @@ scc_status scc_bag_selftest(scc_ctx_t *c, const uint64_t *keys, int64_t n, int32
             stats->bag_inserts = (int64_t)ctr_kind(c->hctl->cn, kKindExpandSingle, kCtrInserts);
             stats->bag_chunk_advances = (int64_t)adv;
         }
+    });
+}
+
+scc_status scc_bag_stats(scc_ctx_t *c, double *rows, int64_t cap, int64_t *n_rows, int64_t *prefix,
+                         int64_t prefix_cap, int64_t *n_rounds) {
+    return guard(c, [&] {
+        if (!n_rows || !n_rounds || cap < 0 || prefix_cap < 0 || (cap > 0 && !rows) || (prefix_cap > 0 && !prefix)) {
+            set_err(c, "bad arguments");
+            throw Fail{SCC_EINVAL};
+        }
+        const int64_t nr = (int64_t)(c->bag_rows.size() / 4);
+        *n_rows = nr;
+        if (std::min(nr, cap) > 0) memcpy(rows, c->bag_rows.data(), sizeof(double) * 4 * (size_t)std::min(nr, cap));
+        *n_rounds = (int64_t)c->bag_prefix.size();
+        const int64_t np = std::min(*n_rounds, prefix_cap);
+        if (np > 0) memcpy(prefix, c->bag_prefix.data(), sizeof(int64_t) * (size_t)np);
     });
 }
 

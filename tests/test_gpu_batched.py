@@ -20,6 +20,9 @@ def test_autotuned_batch_matches_oracle_and_per_graph_calls(gpu):
     opts, rep = autotune.tune(vb, ab, *arrs, sample_arcs=200_000, repeats=1)
     assert (opts.tau, opts.beta) in [(c[0], pytest.approx(c[1])) for c in autotune.CANDIDATES]
     assert len(rep["candidates"]) == len(autotune.CANDIDATES) and rep["sample_graphs"] > 0
+    # the sample is a strict subset; the chosen schedule was also timed on the rest
+    assert 0 < rep["held_out_graphs"] < len(graphs) and rep["sample_graphs"] + rep["held_out_graphs"] == len(graphs)
+    assert rep["held_out_tuned_ms"] > 0 and rep["held_out_default_ms"] > 0
     got = gpu.scc_labels_batched(vb, ab, *arrs, options=opts).cpu().numpy()
     for g, gr in enumerate(graphs):
         assert np.array_equal(got[vb[g]:vb[g + 1]], oracle.scc_graph(gr)), "graph %d" % g
@@ -29,3 +32,36 @@ def test_autotuned_batch_matches_oracle_and_per_graph_calls(gpu):
         dg = gpu.DeviceGraph(n, int(ab[g + 1] - ab[g]), arrs[0][lo:lo + n + 1], arrs[1][int(ab[g]):int(ab[g + 1])],
                              arrs[2][lo:lo + n + 1], arrs[3][int(ab[g]):int(ab[g + 1])])
         assert np.array_equal(gpu.scc_labels(dg).cpu().numpy(), got[vb[g]:vb[g + 1]])
+
+
+def test_batch_split_into_several_unions(gpu):
+    # a batch whose arcs exceed the union limit runs as several disjoint
+    # unions (the path the full 4096-graph batch takes at 2^31 arcs); here the
+    # limit is lowered so that a small batch splits into many unions, one of
+    # them a single graph larger than the limit
+    import torch
+    graphs = graphgen.batched(60, seed=4343, lo_exp=2.0, hi_exp=3.6)
+    graphs.insert(17, graphgen.torus(250, 260, 0.6, seed=4344))
+    vb, ab, oo, oa, io, ia = graphgen.concat(graphs)
+    total = int(ab[-1])
+    limit = max(total // 7, 1000)
+    biggest = int(np.max(np.diff(ab)))
+    assert biggest > limit and total > 3 * limit
+    # unions as the library forms them: consecutive graphs while under the limit
+    unions, g0 = 0, 0
+    while g0 < len(graphs):
+        g1 = g0 + 1
+        while g1 < len(graphs) and ab[g1 + 1] - ab[g0] < limit:
+            g1 += 1
+        unions += 1
+        g0 = g1
+    assert unions >= 3
+    print("[case] batch split", len(graphs), "graphs", total, "arcs, limit", limit, "->", unions, "unions", flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+    arrs = (t(oo), t(oa), t(io), t(ia))
+    got, st = gpu.scc_labels_batched(vb, ab, *arrs, options=gpu.default_options(union_arcs_max=limit),
+                                     return_stats=True)
+    got = got.cpu().numpy()
+    for g, gr in enumerate(graphs):
+        assert np.array_equal(got[vb[g]:vb[g + 1]], oracle.scc_graph(gr)), "graph %d" % g
+    assert st["n_scc"] == sum(len(np.unique(oracle.scc_graph(gr))) for gr in graphs)

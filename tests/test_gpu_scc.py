@@ -29,9 +29,8 @@ def check_labels(scc, g, opts=None, name=""):
     return st
 
 
-def sorted_pairs(p):
-    p = np.asarray(p).reshape(-1, 2)
-    return p[np.lexsort((p[:, 0], p[:, 1]))]
+def as_pairs(p):
+    return np.asarray(p).reshape(-1, 2)
 
 
 def test_tiny_random_graphs(gpu):
@@ -64,7 +63,39 @@ def test_quadratic_reach(gpu, opt):
     src = np.concatenate([np.arange(m), np.arange(m) + m, i])
     dst = np.concatenate([np.arange(m) + m, np.arange(m), j])
     g = graphgen.from_arcs(2 * m, src, dst)
-    check_labels(gpu, g, gpu.default_options(**opt), name="cycle-dag m=%d %s" % (m, opt))
+    st = check_labels(gpu, g, gpu.default_options(**opt), name="cycle-dag m=%d %s" % (m, opt))
+    assert st["restart_rounds"] <= st["rounds_multi"]
+
+
+@pytest.mark.parametrize("first", [0, 1])
+def test_first_slot_families(gpu, first):
+    # the inline first-source slot on every family, including pair-heavy
+    # batches (the quadratic-reach graph) and restarts on a tiny table
+    opts = gpu.default_options(first_slot=first)
+    for g in (graphgen.rmat(13, 16, seed=61), graphgen.knn(40000, 4, 5, 0.01, seed=62),
+              graphgen.grid(150, 160, 0.5, seed=63), graphgen.lattice_oriented(60, 70, 1, seed=64)):
+        check_labels(gpu, g, opts, name="%s first_slot=%d" % (g.name, first))
+    m = 300
+    i, j = np.triu_indices(m, 1)
+    g = graphgen.from_arcs(2 * m, np.concatenate([np.arange(m), np.arange(m) + m, i]),
+                           np.concatenate([np.arange(m) + m, np.arange(m), j]))
+    check_labels(gpu, g, gpu.default_options(first_slot=first, beta=8.0), name="cycle-dag first_slot=%d" % first)
+    n = 20000
+    g = graphgen.from_arcs(n, np.arange(n - 1), np.arange(1, n))
+    st = check_labels(gpu, g, gpu.default_options(first_slot=first, table_init=1024, table_floor=0.0),
+                      name="path20000 small table first_slot=%d" % first)
+    if not first:
+        assert st["table_restarts"] > 0
+
+
+def test_forced_small_table_restarts(gpu):
+    # a path: the first search splits it into two long subproblems, so the
+    # next batch's sources reach thousands of vertices in some direction,
+    # far more than a 1024-slot table holds
+    n = 20000
+    g = graphgen.from_arcs(n, np.arange(n - 1), np.arange(1, n))
+    st = check_labels(gpu, g, gpu.default_options(table_init=1024, table_floor=0.0), name="path20000 small table")
+    assert st["table_restarts"] > 0
 
 
 def test_empty_graph(gpu):
@@ -98,12 +129,12 @@ def test_config0_full_size(gpu):
     dict(arcs_per_lane=1, tau=512, lambda_log2=10),
     dict(lambda_log2=6, sigma=1, kappa=0),
     dict(table_init=1024), dict(trim=0), dict(seed=12345), dict(table_floor=0.0), dict(table_floor=0.3),
+    dict(first_slot=1), dict(first_slot=1, tau=1), dict(first_slot=1, table_init=1024, table_floor=0.0),
+    dict(first_slot=1, arcs_per_lane=2), dict(vgc_measure=1), dict(vgc_measure=1, tau=64, first_slot=1),
 ])
 def test_schedule_invariance(gpu, opt):
     g = graphgen.torus(100, 120, 0.55, seed=77)
-    st = check_labels(gpu, g, gpu.default_options(**opt), name="torus100x120 %s" % opt)
-    if opt.get("table_init") == 1024:
-        assert st["table_restarts"] >= 0
+    check_labels(gpu, g, gpu.default_options(**opt), name="torus100x120 %s" % opt)
 
 
 def test_rounds_vgc_not_more_than_bfs(gpu):
@@ -115,6 +146,43 @@ def test_rounds_vgc_not_more_than_bfs(gpu):
     _, vgc = gpu.scc_labels(dg, gpu.default_options(tau=512, seed=3), return_stats=True)
     assert vgc["rounds_first"] <= plain["rounds_first"]
     assert vgc["rounds_first"] + vgc["rounds_multi"] <= plain["rounds_first"] + plain["rounds_multi"]
+
+
+def test_reach_rounds_equal_bfs_levels_without_vgc(gpu):
+    # Algorithm 2: with tau <= 1 (no local search) a search runs one frontier
+    # round per BFS level, so its rounds are the largest BFS depth of its
+    # sources plus one (the last round finds nothing); local search can only
+    # merge rounds
+    rng = np.random.default_rng(31)
+    graphs = [graphgen.grid(60, 70, 0.7, seed=41), graphgen.torus(50, 50, 0.55, seed=42),
+              graphgen.from_arcs(3000, np.arange(2999), np.arange(1, 3000)), graphgen.rmat(11, 8, seed=43),
+              graphgen.knn(20000, 4, 5, 0.01, seed=44)]
+    for g in graphs:
+        dg = gpu.to_device(g)
+        labels = np.zeros(g.n, np.int32)
+        if g.n > 5000:
+            labels[rng.random(g.n) < 0.1] = -1
+        cand = np.nonzero(labels >= 0)[0]
+        for k in (1, 3, 40):
+            src = rng.permutation(cand)[:k].astype(np.int32)
+            for d in (0, 1):
+                off, adj = (g.out_off, g.out_adj) if d == 0 else (g.in_off, g.in_adj)
+                depth = int(oracle.bfs_depths(g.n, off, adj, labels, src).max())
+                key = "rounds_first" if k == 1 else "rounds_multi"
+                for dense in ((0, 1) if k == 1 else (0,)):
+                    say("rounds", g.name, "k", k, "dir", d, "dense", dense)
+                    # a table large enough for every pair: no restart, so the
+                    # round count covers the whole search
+                    big = 1 << int(np.ceil(np.log2(2 * k * g.n + 1024)))
+                    got, st = gpu.scc_reach(dg, src, labels, direction=d, return_stats=True,
+                                            options=gpu.default_options(tau=1, dense=dense, table_init=big))
+                    assert st["table_restarts"] == 0
+                    assert st[key] == depth + 1, (g.name, k, d, dense, st[key], depth)
+                    want = oracle.reach_pairs(g.n, off, adj, labels, src)
+                    assert np.array_equal(as_pairs(got.cpu().numpy()), want)
+                _, st = gpu.scc_reach(dg, src, labels, direction=d, return_stats=True,
+                                      options=gpu.default_options(tau=2048))
+                assert st[key] <= depth + 1
 
 
 def test_reach_matches_oracle(gpu):
@@ -134,7 +202,7 @@ def test_reach_matches_oracle(gpu):
                     got = gpu.scc_reach(dg, src, labels, direction=d).cpu().numpy()
                     off, adj = (g.out_off, g.out_adj) if d == 0 else (g.in_off, g.in_adj)
                     want = oracle.reach_pairs(g.n, off, adj, labels, src)
-                    assert np.array_equal(sorted_pairs(got), want)
+                    assert np.array_equal(as_pairs(got), want)
 
 
 def test_reach_rejects_bad_sources(gpu):
@@ -153,7 +221,7 @@ def test_reach_rejects_bad_sources(gpu):
     # the context still works after errors
     got = gpu.scc_reach(dg, [0], np.zeros(g.n, np.int32)).cpu().numpy()
     want = oracle.reach_pairs(g.n, g.out_off, g.out_adj, np.zeros(g.n, np.int32), [0])
-    assert np.array_equal(sorted_pairs(got), want)
+    assert np.array_equal(as_pairs(got), want)
 
 
 def test_invalid_graph_rejected(gpu):
@@ -188,9 +256,44 @@ def test_hash_bag_extract_is_inserted_multiset(gpu):
         out, st = gpu.bag_selftest(torch.from_numpy(keys).cuda(), rounds,
                                    gpu.default_options(lambda_log2=lam), return_stats=True)
         got = np.sort(out.cpu().numpy())
-        assert np.array_equal(got, oracle.hashbag_model([keys])[0])
+        assert np.array_equal(got, np.sort(np.concatenate(oracle.hashbag_model(
+            [keys[r::rounds] for r in range(rounds)]))))
         if n >= 100000:
             assert st["bag_chunk_advances"] > 0
+
+
+def test_hash_bag_theorem1_load_and_prefix(gpu):
+    # Theorem 1 / Appendix A with alpha = 1/2: a chunk is left at a load in
+    # [1/4, 3/4] w.h.p. once chunks are large against the inserts in flight
+    # (k = Omega(P sigma): here 4096 wavefronts of 64 against chunks of 2^22),
+    # and s elements occupy the first O(s + lambda) slots
+    import torch
+    loads, forced = [], []
+    for seed in range(20):
+        s = 12_000_000 + 500_000 * seed
+        keys = torch.arange(s, dtype=torch.int64, device="cuda") * 2654435761 + seed
+        say("bag theorem1 seed", seed, "s", s)
+        opts = gpu.default_options(lambda_log2=22, sigma=50, alpha=0.5, seed=seed + 1)
+        out = gpu.bag_selftest(keys, 1, opts)
+        assert out.numel() == s
+        rows, prefix = gpu.bag_stats()
+        loads += [r[2] for r in rows if r[3] == 0]
+        forced += [r[2] for r in rows if r[3] == 1]
+        assert len(prefix) == 1 and prefix[0] <= 8 * (s + (1 << 22)), (prefix, s)
+    say("bag loads at a move: sampled", np.round(sorted(loads), 3), "probe limit", np.round(sorted(forced), 3))
+    assert loads, "no chunk was left by its samples"
+    assert min(loads) >= 0.25 and max(loads) <= 0.75, (min(loads), max(loads))
+    # the probe limit is the rare fallback; a chunk it ends is still well used
+    assert len(forced) <= 0.2 * (len(loads) + len(forced)) and all(x >= 0.125 for x in forced)
+
+
+def test_bag_lambda_change_on_one_context(gpu):
+    # a small first chunk on one call, the automatic one on the next: each
+    # search lane keeps a chunk count that fits its own buffers
+    g = graphgen.knn(60000, 6, 5, 0.01, seed=45)
+    check_labels(gpu, g, gpu.default_options(lambda_log2=6), name="knn60k lambda 2^6")
+    check_labels(gpu, g, gpu.default_options(), name="knn60k lambda auto")
+    check_labels(gpu, g, gpu.default_options(lambda_log2=6), name="knn60k lambda 2^6 again")
 
 
 def test_batched_matches_per_graph_oracle(gpu):
@@ -243,7 +346,7 @@ def test_dense_reach_matches_oracle(gpu):
                                 options=gpu.default_options(dense=dense)).cpu().numpy()
             off, adj = (g.out_off, g.out_adj) if d == 0 else (g.in_off, g.in_adj)
             want = oracle.reach_pairs(g.n, off, adj, lab, [int(np.argmax(np.diff(g.out_off)))])
-            assert np.array_equal(sorted_pairs(got), want)
+            assert np.array_equal(as_pairs(got), want)
 
 
 def test_policy_and_exploration_do_not_change_labels(gpu):

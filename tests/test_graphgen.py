@@ -94,3 +94,48 @@ def test_from_arcs_rejects_bad_input():
         graphgen.from_arcs(3, [0, 5], [1, 2])
     g = graphgen.from_arcs(3, [0, 0, 1], [1, 1, 1])
     assert g.m == 3  # duplicates and self loops kept unless dedup
+
+
+def test_oriented_lattices_match_definition():
+    # the paper's lattices (Section 6) recomputed arc by arc from the draws
+    rows, cols, seed = 6, 8, 77
+    n = rows * cols
+    for mode in (0, 1):
+        g = graphgen.lattice_oriented(rows, cols, mode, seed)
+        src = _csr_ok(g)
+        want = set()
+        for u in range(n):
+            r, c = divmod(u, cols)
+            east, south = r * cols + (c + 1) % cols, ((r + 1) % rows) * cols + c
+            if mode == 0:
+                nbrs = [east, r * cols + (c - 1) % cols, south, ((r - 1) % rows) * cols + c]
+                for d, v in enumerate(nbrs):  # u's own draw for each adjacent vertex
+                    if graphgen.unif(seed, 2, 4 * u + d) < 0.5:
+                        want.add((u, v))
+                    else:
+                        want.add((v, u))
+            else:
+                for j, v in enumerate((east, south)):  # u owns its east and south edges
+                    if graphgen.unif(seed, 3, 4 * u + 2 * j) < 0.3:
+                        want.add((u, v))
+                    if graphgen.unif(seed, 3, 4 * u + 2 * j + 1) < 0.3:
+                        want.add((v, u))
+        got = set(zip(src.tolist(), g.out_adj.tolist()))
+        assert got == want, mode
+        assert len(got) == g.m  # duplicates removed
+
+
+def test_oriented_lattice_arc_density():
+    # Table 3: SQR has 300M arcs on 2e8 edges (1.5 per edge), SQR' 120M (0.6)
+    for mode, per_edge in ((0, 1.5), (1, 0.6)):
+        g = graphgen.lattice_oriented(300, 400, mode, 5)
+        assert abs(g.m / (2 * g.n) - per_edge) < 0.01
+        src = np.repeat(np.arange(g.n), np.diff(g.out_off))
+        assert not np.any(src == g.out_adj)
+    # mode 0 orients every edge at least one way
+    g = graphgen.lattice_oriented(50, 60, 0, 6)
+    und = set()
+    src = np.repeat(np.arange(g.n), np.diff(g.out_off))
+    for u, v in zip(src.tolist(), g.out_adj.tolist()):
+        und.add((min(u, v), max(u, v)))
+    assert len(und) == 2 * g.n

@@ -77,3 +77,19 @@ def test_autotune_subset_takes_whole_graphs():
     vb3, ab3, (oo3, oa3, _, _) = autotune._subset(vb, ab, arrays, [1])
     assert list(vb3) == [0, 3] and list(ab3) == [0, 3]
     assert oo3.tolist() == [0, 1, 2, 3] and oa3.tolist() == [1, 2, 0]
+
+
+def test_autotune_sample_is_a_strict_subset_and_held_out_is_the_rest():
+    import numpy as np
+
+    from paper_2303_04934_amd import autotune
+    for G, arcs_each in ((4096, 1000), (4097, 999), (7, 3), (2, 5)):
+        vb = np.arange(G + 1, dtype=np.int64) * 10
+        ab = np.arange(G + 1, dtype=np.int64) * arcs_each
+        for seed in (0, 1, 5):
+            idx, rest = autotune.split(vb, ab, seed=seed)
+            assert len(idx) >= 1 and len(rest) >= 1, (G, seed)
+            assert sorted(idx + rest) == list(range(G))
+            assert len(set(idx) & set(rest)) == 0
+            # every second graph: the sample keeps about half the batch
+            assert abs(len(idx) - G / 2) <= 1
