@@ -235,6 +235,30 @@ const char *scc_last_error(const scc_ctx_t *ctx);
 scc_status scc_labels(scc_ctx_t *ctx, const scc_graph_t *g, int32_t *labels_out, const scc_options_t *opt,
                       scc_stats_t *stats);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and result as scc_labels, but every scratch buffer of the call
+ * (per-vertex state, visited bitmaps, both reach tables, frontiers, hash
+ * bags) is carved from one fixed device array of 512 MiB that the library
+ * holds per device from load until the process ends; the call itself makes
+ * no hipMalloc, hipFree or other allocating call (the context's own control
+ * block and pinned host mirror were allocated by scc_create).
+ * Limits:
+ *   - about 1.5 million vertices with the default options (the carve takes
+ *     roughly 340 bytes per vertex, rounded up to powers of two); a larger
+ *     graph returns SCC_ECAPACITY before any work is queued;
+ *   - reach tables stop at next_pow2(max(1024, 4n)) slots and frontiers at
+ *     2n entries per round: a search that outgrows them returns
+ *     SCC_ECAPACITY (scc_labels would grow them);
+ *   - options.timing and options.trace must be 0 (they create events), and
+ *     the stats carry no phase times.
+ * Every call on a device shares that device's array and keeps the previous
+ * call's contents: each call clears what must start empty, so calls in
+ * sequence are independent, but calls that overlap on one GPU (from other
+ * contexts, streams or threads) race and give undefined results. */
+scc_status scc_labels_static(scc_ctx_t *ctx, const scc_graph_t *g, int32_t *labels_out, const scc_options_t *opt,
+                             scc_stats_t *stats);
+
 /* Reachability pairs (Section 2, "Reachability Search"; the MultiReach of
  * Algorithm 1).  dir = 0 searches G (out_*), dir = 1 searches G^T (in_*).
  * sources: device int32[k], distinct, with labels[s] >= 0.  labels: device

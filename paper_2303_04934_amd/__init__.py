@@ -19,7 +19,7 @@ import numpy as np
 from . import _native
 from ._native import POLICY_FLOATS, STATUS_NAMES, Options, Stats
 
-__all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_cc", "scc_reach",
+__all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_labels_static", "scc_cc", "scc_reach",
            "scc_labels_batched", "bag_selftest", "bag_stats", "policy_load", "policy_eval", "trace_read", "version",
            "POLICY_FLOATS", "TRACE_FIELDS"]
 
@@ -116,6 +116,21 @@ def scc_labels(dg: DeviceGraph, options: Options | None = None, return_stats: bo
     _check(lib, ctx, rc)
     out = out[:dg.n]
     return (out, st.as_dict()) if return_stats else out
+
+
+def scc_labels_static(dg: DeviceGraph, out, options: Options | None = None, return_stats: bool = False):
+    """scc_labels without device allocation: scratch comes from the library's
+    fixed per-device array (see scc_labels_static in hipscc.h).  ``out`` is a
+    caller-allocated int32 device tensor of at least n elements."""
+    lib = _native.load()
+    ctx = _current(dg.out_off)
+    st = Stats()
+    g = dg.c_struct()
+    rc = lib.scc_labels_static(ctx, ctypes.byref(g), out.data_ptr(), ctypes.byref(options) if options else None,
+                               ctypes.byref(st))
+    _check(lib, ctx, rc)
+    res = out[:dg.n]
+    return (res, st.as_dict()) if return_stats else res
 
 
 def scc_cc(dg: DeviceGraph, options: Options | None = None, return_stats: bool = False, out=None):

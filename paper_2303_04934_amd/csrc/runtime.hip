@@ -16,8 +16,10 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -120,6 +122,10 @@ struct scc_ctx {
     size_t pev_used = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> plog;
     Policy policy;
+    // scc_labels_static: this device's copy of the static scratch array, and
+    // whether the current call must not allocate (buffers are carved views)
+    uint8_t *scratch = nullptr;
+    bool noalloc = false;
     // statistics of the last scc_bag_selftest: (round, chunk, load, cause) for
     // every chunk left before its round's ExtractAll, and each round's used
     // prefix
@@ -161,6 +167,11 @@ void ensure(scc_ctx *c, DevBuf<T> &b, uint64_t n, bool *grew = nullptr) {
     if (grew) *grew = false;
     if (n == 0) n = 1;
     if (b.cap >= n) return;
+    if (c->noalloc) {
+        set_err(c, "a buffer of %llu elements exceeds its part of the static scratch (%llu)", (unsigned long long)n,
+                (unsigned long long)b.cap);
+        throw Fail{SCC_ECAPACITY};
+    }
     if (b.p) {
         HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(hipFree(b.p));
@@ -1000,7 +1011,7 @@ void fill_counters(scc_ctx *c, scc_stats_t *st, int64_t n) {
 void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_options_t &o, scc_stats_t *st) {
     const int32_t n = g.n;
     if (n == 0) return;
-    const bool ph = st != nullptr;
+    const bool ph = st != nullptr && !c->noalloc;  // phase events are created on first use
     ensure_vertex_state(c, n);
     if (o.validate) validate_graph(c, g);
     // per-call state: the relabel accumulators and stamps are cleared only
@@ -1411,6 +1422,140 @@ void accumulate_stats(scc_stats_t &acc, const scc_stats_t &st) {
     }
 }
 
+// ------------------------------------------------------ static scratch --
+// scc_labels_static carves every per-call buffer of scc_labels from one fixed
+// device array instead of allocating.  The array is file-scope device memory:
+// each device the library runs on holds its own copy from module load until
+// the process ends.  Host code must not pass the symbol itself to a kernel
+// (on the host it only names the array); scc_create looks up this device's
+// address with hipGetSymbolAddress and every use goes through that address.
+constexpr uint64_t kStaticScratchBytes = 512ull << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[kMaxDevices] = {};
+
+// This device's address of the scratch array (looked up once per device,
+// with the device current).
+uint8_t *scratch_address(scc_ctx *c) {
+    if (c->device < 0 || c->device >= kMaxDevices) {
+        set_err(c, "device %d beyond the static scratch table", c->device);
+        throw Fail{SCC_EINVAL};
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[c->device]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_err(c, "hipGetSymbolAddress returned no address for the static scratch");
+            throw Fail{SCC_EHIP};
+        }
+        g_scratch[c->device] = (uint8_t *)p;
+    }
+    return g_scratch[c->device];
+}
+
+// Everything run_scc allocates or keeps between calls, swapped out while a
+// static call runs on carved views.
+struct BufSet {
+    DevBuf<int32_t> label, aux, stamp, srcvert, srclab, fin;
+    DevBuf<uint32_t> invp;
+    DevBuf<unsigned long long> sig_out, sig_in;
+    DevBuf<uint32_t> vis[2], bm[2][2];
+    DevBuf<uint64_t> Tout, Tin, F[2], heavy[2], bag_slots[2];
+    DevBuf<uint32_t> bag_cnt[2];
+    DevBuf<int32_t> firstS[2];
+    uint32_t bag_nchunks[2], bag_lam_log2[2];
+    bool tables_dirty;
+    int64_t vclean_n, first_clean_n;
+    int32_t stamp_next;
+    uint64_t table_slots_max;
+};
+
+void bufs_save(const scc_ctx *c, BufSet &b) {
+    b.label = c->label; b.aux = c->aux; b.stamp = c->stamp; b.srcvert = c->srcvert; b.srclab = c->srclab;
+    b.fin = c->fin; b.invp = c->invp; b.sig_out = c->sig_out; b.sig_in = c->sig_in;
+    for (int i = 0; i < 2; i++) {
+        b.vis[i] = c->vis[i]; b.bm[i][0] = c->bm[i][0]; b.bm[i][1] = c->bm[i][1];
+        b.F[i] = c->F[i]; b.heavy[i] = c->heavy[i]; b.bag_slots[i] = c->bag_slots[i]; b.bag_cnt[i] = c->bag_cnt[i];
+        b.bag_nchunks[i] = c->bag_nchunks[i]; b.bag_lam_log2[i] = c->bag_lam_log2[i];
+        b.firstS[i] = c->firstS[i];
+    }
+    b.Tout = c->Tout; b.Tin = c->Tin;
+    b.tables_dirty = c->tables_dirty; b.vclean_n = c->vclean_n; b.stamp_next = c->stamp_next;
+    b.first_clean_n = c->first_clean_n;
+    b.table_slots_max = c->table_slots_max;
+}
+
+void bufs_load(scc_ctx *c, const BufSet &b) {
+    c->label = b.label; c->aux = b.aux; c->stamp = b.stamp; c->srcvert = b.srcvert; c->srclab = b.srclab;
+    c->fin = b.fin; c->invp = b.invp; c->sig_out = b.sig_out; c->sig_in = b.sig_in;
+    for (int i = 0; i < 2; i++) {
+        c->vis[i] = b.vis[i]; c->bm[i][0] = b.bm[i][0]; c->bm[i][1] = b.bm[i][1];
+        c->F[i] = b.F[i]; c->heavy[i] = b.heavy[i]; c->bag_slots[i] = b.bag_slots[i]; c->bag_cnt[i] = b.bag_cnt[i];
+        c->bag_nchunks[i] = b.bag_nchunks[i]; c->bag_lam_log2[i] = b.bag_lam_log2[i];
+        c->firstS[i] = b.firstS[i];
+    }
+    c->Tout = b.Tout; c->Tin = b.Tin;
+    c->tables_dirty = b.tables_dirty; c->vclean_n = b.vclean_n; c->stamp_next = b.stamp_next;
+    c->first_clean_n = b.first_clean_n;
+    c->table_slots_max = b.table_slots_max;
+}
+
+// The carve of the static scratch for an n-vertex graph: the buffers
+// scc_labels sizes for it (per-vertex state, bitmaps, two reach tables of
+// next_pow2(max(1024, 4n)) slots, and per lane a frontier, a heavy list and
+// a hash bag for 2n entries per round).  With base == nullptr only the size
+// is computed.  Returns the bytes used.
+uint64_t static_carve(const scc_options_t &o, int64_t n, uint8_t *base, BufSet *out) {
+    uint64_t at = 0;
+    auto take = [&](auto &buf, uint64_t elems) {
+        using T = typename std::remove_reference<decltype(*buf.p)>::type;
+        elems = std::max<uint64_t>(elems, 1);
+        at = (at + 255) & ~255ull;
+        if (base) {
+            buf.p = reinterpret_cast<T *>(base + at);
+            buf.cap = elems;
+        }
+        at += elems * sizeof(T);
+    };
+    BufSet tmp;
+    BufSet &b = out ? *out : tmp;
+    const uint64_t nv = (uint64_t)n;
+    take(b.label, nv); take(b.aux, nv); take(b.stamp, nv); take(b.fin, nv); take(b.srcvert, nv);
+    take(b.srclab, nv); take(b.invp, nv); take(b.sig_out, nv); take(b.sig_in, nv);
+    for (int i = 0; i < 2; i++) {
+        take(b.vis[i], nv / 32 + 2);
+        take(b.bm[i][0], nv / 32 + 2);
+        take(b.bm[i][1], nv / 32 + 2);
+    }
+    const uint64_t T = next_pow2(std::max<uint64_t>(1024, 4 * nv));
+    take(b.Tout, T);
+    take(b.Tin, T);
+    take(b.firstS[0], nv);
+    take(b.firstS[1], nv);
+    const uint64_t E = 2 * nv;
+    const uint32_t lam = lam_log2_for(o, nv);
+    uint32_t nch = 1;
+    while (((1ull << lam) << (nch - 1)) < 2 * (E + (1ull << lam))) nch++;
+    const uint64_t bag = (1ull << lam) << (nch - 1);
+    for (int i = 0; i < 2; i++) {
+        take(b.F[i], E + kWave);
+        take(b.heavy[i], 2 * (E + kWave));
+        take(b.bag_slots[i], bag);
+        take(b.bag_cnt[i], bag >> kStripeLog2);
+        b.bag_nchunks[i] = 0;
+        b.bag_lam_log2[i] = 0xffffffffu;  // no lambda yet: the first sizing clears the counters
+    }
+    b.table_slots_max = T;
+    b.tables_dirty = true;  // the array keeps whatever the last call on this device left
+    b.vclean_n = 0;
+    b.first_clean_n = 0;
+    b.stamp_next = 1;
+    return (at + 255) & ~255ull;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1469,6 +1614,7 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
         }
         HIPCHK(hipMalloc((void **)&c->dctl, sizeof(DevCtl)));
         HIPCHK(hipHostMalloc((void **)&c->hctl, sizeof(DevCtl), hipHostMallocDefault));
+        c->scratch = scratch_address(c);
         reset_ctl(c);
         HIPCHK(hipStreamSynchronize(c->stream));
     });
@@ -1517,6 +1663,47 @@ scc_status scc_labels(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, c
         scc_options_t o = opt ? *opt : defaults();
         check_opts(c, o);
         const double t0 = now_ms();
+        init_call(c, stats, g->n, g->m, &o);
+        GraphDev gd{g->n, g->m, g->out_off, g->out_adj, g->in_off, g->in_adj};
+        run_scc(c, gd, labels_out, o, stats);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (stats) stats->ms_total = now_ms() - t0;
+    });
+}
+
+scc_status scc_labels_static(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, const scc_options_t *opt,
+                             scc_stats_t *stats) {
+    return guard(c, [&] {
+        check_graph_args(c, g);
+        if (g->n > 0 && !labels_out) { set_err(c, "labels_out is NULL"); throw Fail{SCC_EINVAL}; }
+        scc_options_t o = opt ? *opt : defaults();
+        check_opts(c, o);
+        if (o.timing || o.trace) {
+            set_err(c, "scc_labels_static records no events: options.timing and options.trace must be 0");
+            throw Fail{SCC_EINVAL};
+        }
+        if (!c->scratch) { set_err(c, "internal: static scratch address not set"); throw Fail{SCC_EINTERNAL}; }
+        const uint64_t need = static_carve(o, g->n, nullptr, nullptr);
+        if (need > kStaticScratchBytes) {
+            set_err(c, "graph with n = %d needs %llu bytes of static scratch, more than its %llu", g->n,
+                    (unsigned long long)need, (unsigned long long)kStaticScratchBytes);
+            throw Fail{SCC_ECAPACITY};
+        }
+        const double t0 = now_ms();
+        BufSet heap;
+        bufs_save(c, heap);
+        struct Restore {
+            scc_ctx *c;
+            BufSet &heap;
+            ~Restore() {
+                c->noalloc = false;
+                bufs_load(c, heap);
+            }
+        } restore{c, heap};
+        BufSet carved;
+        static_carve(o, g->n, c->scratch, &carved);
+        bufs_load(c, carved);
+        c->noalloc = true;
         init_call(c, stats, g->n, g->m, &o);
         GraphDev gd{g->n, g->m, g->out_off, g->out_adj, g->in_off, g->in_adj};
         run_scc(c, gd, labels_out, o, stats);
