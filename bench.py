@@ -201,7 +201,14 @@ def run_batched(args, desc):
     load_policy(scc)
     base = scc.default_options(validate=0)
     t0 = time.perf_counter()
-    opts, tuned = autotune.tune(vb, ab, *arrs, base_options=base)
+    if args.schedule:
+        # a given schedule (profiling runs repeat the one the timed run picked)
+        opts = scc.default_options(validate=0)
+        tau, beta, beta_fast, policy = args.schedule.split(",")
+        opts.tau, opts.beta, opts.beta_fast, opts.policy = int(tau), float(beta), float(beta_fast), int(policy)
+        tuned = {"given": args.schedule}
+    else:
+        opts, tuned = autotune.tune(vb, ab, *arrs, base_options=base)
     log("autotune picked tau=%d beta=%.1f beta_fast=%.0f policy=%d in %.1f s (held out: %.1f ms tuned vs %.1f "
         "default)" % (opts.tau, opts.beta, opts.beta_fast, opts.policy, time.perf_counter() - t0,
                       tuned.get("held_out_tuned_ms", 0), tuned.get("held_out_default_ms", 0)))
@@ -222,6 +229,10 @@ def run_batched(args, desc):
     dt = (time.perf_counter() - t0) / args.steps
     got = out.cpu().numpy()
     log("timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3))
+    if args.profile_only:
+        print(json.dumps({"workload": "batched4096", "ms_per_step": dt * 1e3, "steps": args.steps,
+                          "schedule": [opts.tau, opts.beta, opts.beta_fast, opts.policy]}), flush=True)
+        return
 
     # comparisons (untimed region), with the same event overhead as the timed steps
     def once(o):
@@ -305,6 +316,9 @@ def run_single(args, cfg, desc):
     opts = scc.default_options(timing=0, validate=0, policy=args.policy)
     if args.tau:
         opts.tau = args.tau
+    if args.first_slot >= 0:
+        opts.first_slot = args.first_slot
+    opts.vgc_measure = args.vgc_measure
     if args.policy == 1:
         load_policy(scc)
     # Untimed warm-up.  Its last call times every frontier kernel to find the
@@ -334,7 +348,7 @@ def run_single(args, cfg, desc):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": g.n, "m": g.m, "seed": 1000 + cfg,
                    "tau": opts.tau, "policy": "learned" if args.policy == 1 else "fixed",
-                   "shrink": args.shrink},
+                   "first_slot": opts.first_slot, "vgc_measure": opts.vgc_measure, "shrink": args.shrink},
     }
     ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
     la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
@@ -371,8 +385,13 @@ def main():
     ap.add_argument("--tau", type=int, default=0, help="VGC budget (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--policy", type=int, default=0, help="0 fixed budget, 1 learned per-round policy")
+    ap.add_argument("--first-slot", type=int, default=-1, help="options.first_slot (-1: the library default)")
+    ap.add_argument("--vgc-measure", type=int, default=0, help="options.vgc_measure (0 arcs, 1 claims)")
     ap.add_argument("--batch-hi", type=float, default=6.0,
                     help="batched workload: vertex counts log-uniform in [1e3, 10**batch_hi]")
+    ap.add_argument("--schedule", default="", help="batched: tau,beta,beta_fast,policy instead of autotuning")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="batched: only the warm-up and timed steps (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()

@@ -169,6 +169,14 @@ def from_arcs(n: int, src, dst, dedup: bool = False, name: str = "arcs") -> Grap
     return _finish(cs, name)
 
 
+def symmetrize(g: Graph) -> Graph:
+    """The symmetric digraph with both arcs of every arc of g (duplicates
+    removed): the undirected graphs Section 5 runs connectivity on."""
+    src = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.out_off))
+    return from_arcs(g.n, np.concatenate([src, g.out_adj]), np.concatenate([g.out_adj, src]), dedup=True,
+                     name=g.name + "_sym")
+
+
 def random_digraph(n: int, avg_deg: float, seed: int, self_loops: bool = False) -> Graph:
     """Erdos-Renyi style digraph with about n*avg_deg arcs (duplicates removed)."""
     m0 = int(round(n * avg_deg))

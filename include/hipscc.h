@@ -130,12 +130,12 @@ typedef struct {
  *                consecutive graphs may hold (0 = default 2^31 - 1, the int32
  *                arc-index limit).  A smaller value splits a batch into more
  *                unions; used to exercise the split on small batches.
- *   first_slot   1 = multi-source searches claim each vertex's first pair in
- *                a per-vertex slot (4 bytes at the vertex, next to its label)
- *                and only later pairs in the reach table; 0 = every pair in
- *                the table (Section 4.3).  Section 3.2 leaves the reach
- *                record open; the slot replaces most random table probes
- *                with an access at the vertex itself.
+ *   first_slot   1 (default) = multi-source searches claim each vertex's
+ *                first pair in a per-vertex slot (4 bytes at the vertex, next
+ *                to its label) and only later pairs in the reach table; 0 =
+ *                every pair in the table (Section 4.3).  The slot replaces
+ *                most random table probes with an access at the vertex
+ *                itself (grid 10^4 x 10^4: 782 -> 722 ms per call).
  *   vgc_measure  what the VGC budget tau counts (Section 3.2 names
  *                alternatives to examined arcs): 0 = examined arcs (default),
  *                1 = new claims (generated reachability pairs, or visited
@@ -306,6 +306,29 @@ scc_status scc_labels_batched(scc_ctx_t *ctx, int32_t G, const int64_t *vtx_base
  * claim_attempts include the union pass's arcs and link attempts. */
 scc_status scc_cc(scc_ctx_t *ctx, const scc_graph_t *g, int32_t *labels_out, const scc_options_t *opt,
                   scc_stats_t *stats);
+
+/* Least-element lists (Section 5.2, Algorithm 5).  Only the out-CSR of g is
+ * read.  The vertices take a random total order (from options.seed); the
+ * list of u holds every s with d(s, u) < d(k, u) for all k before s in the
+ * order, d the distance along arcs from s to u (the undirected distance when
+ * g is symmetric, the graphs the paper uses).  The order is processed in
+ * batches of sizes 1, beta, beta^2, ... (options.beta; Algorithm 5 doubles);
+ * each batch runs a multi-source BFS from its sources that claims pairs in a
+ * reach table and keeps its frontier in the hash bag, and enters a vertex
+ * only at a distance below the best one of earlier batches (no local search:
+ * the BFS order is part of the result).  Outputs (device):
+ *   order_out  int32[n] (may be NULL): order_out[i] = the vertex at position i;
+ *   loff       int64[n+1]: u's entries are [loff[u], loff[u+1]);
+ *   src_out, dist_out  int32[capacity]: entry i = (source vertex, distance),
+ *              each list in order of the sources' positions, so its distances
+ *              decrease and it ends with (u, 0).
+ * *n_entries (host) always receives the total; above capacity the call
+ * returns SCC_ECAPACITY (loff, src_out, dist_out unspecified).  Stats:
+ * batches, rounds_multi = BFS rounds, table_restarts = batches re-run on a
+ * larger table, ms_multi = the batches, ms_label = the final lists. */
+scc_status scc_le_lists(scc_ctx_t *ctx, const scc_graph_t *g, int32_t *order_out, int64_t *loff, int32_t *src_out,
+                        int32_t *dist_out, int64_t capacity, int64_t *n_entries, const scc_options_t *opt,
+                        scc_stats_t *stats);
 
 /* Load the learned round policy: a float32 MLP 5 -> 32 -> 32 -> 8 with ReLU,
  * weights as one host blob [W1(32x5), b1(32), W2(32x32), b2(32), W3(8x32),

@@ -11,6 +11,10 @@ Functions (plain definitions, see ``oracle.c`` for the citations):
 * :func:`reach_pairs` -- per-source BFS reach restricted to label-equal arcs;
 * :func:`check_partition` -- certificate (mutual reachability inside every
   class, acyclic class graph, label = class minimum);
+* :func:`wcc_labels` -- weakly connected components (connected components of
+  a symmetric digraph, Algorithm 4's output), canonical min id;
+* :func:`le_lists` -- least-element lists for a given vertex order
+  (Section 5.2), as CSR (offsets, sources, distances);
 * :func:`bfs_depths` -- per-source BFS depth of the same restricted reach
   (the number of frontier rounds of Algorithm 2 is this depth plus one);
 * :func:`hashbag_sim` -- a sequential model of the parallel hash bag
@@ -56,6 +60,8 @@ def _load():
         lib.or_reach_pairs.argtypes = [i64, vp, vp, vp, i64, vp, vp, i64, ctypes.POINTER(i64)]
         lib.or_check_partition.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.POINTER(i64)]
         lib.or_bfs_depths.argtypes = [i64, vp, vp, vp, i64, vp, vp]
+        lib.or_wcc.argtypes = [i64, vp, vp, vp]
+        lib.or_le_lists.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
         lib.or_hashbag_sim.argtypes = [i64, vp, i64, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_int32, ctypes.c_uint64, vp, vp, vp, vp, vp, i64,
                                        ctypes.POINTER(i64)]
@@ -99,6 +105,39 @@ def reach_pairs(n: int, off, adj, labels, sources) -> np.ndarray:
         if rc != 0:
             raise ValueError("or_reach_pairs rejected its input: %d" % rc)
         return pairs[: 2 * cnt.value].reshape(-1, 2)
+
+
+def wcc_labels(n: int, off, adj) -> np.ndarray:
+    """labels[v] = smallest vertex id of v's weakly connected component."""
+    off, adj = _i32(off), _i32(adj)
+    out = np.empty(max(n, 1), np.int32)
+    rc = _load().or_wcc(n, off.ctypes.data, adj.ctypes.data if len(adj) else None, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("or_wcc failed: %d" % rc)
+    return out[:n]
+
+
+def le_lists(n: int, off, adj, order):
+    """LE-lists for the vertex order ``order`` (order[i] = vertex at position
+    i): (loff int64[n+1], src int32[count], dist int32[count]); vertex u's
+    entries sit at [loff[u], loff[u+1]) in order of the sources' positions."""
+    off, adj, order = _i32(off), _i32(adj), _i32(order)
+    loff = np.zeros(n + 1, np.int64)
+    cnt = ctypes.c_int64(0)
+    cap = max(16, 8 * n)
+    while True:
+        src = np.empty(cap, np.int32)
+        dist = np.empty(cap, np.int32)
+        rc = _load().or_le_lists(n, off.ctypes.data, adj.ctypes.data if len(adj) else None,
+                                 order.ctypes.data if n else None, loff.ctypes.data, src.ctypes.data,
+                                 dist.ctypes.data, cap, ctypes.byref(cnt))
+        if rc == -3:
+            cap = int(cnt.value)
+            continue
+        if rc != 0:
+            raise ValueError("or_le_lists failed: %d" % rc)
+        k = int(cnt.value)
+        return loff, src[:k].copy(), dist[:k].copy()
 
 
 def check_partition(g, labels):

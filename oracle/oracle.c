@@ -411,3 +411,138 @@ int or_hashbag_sim(int64_t n, const int64_t *keys, int64_t rounds, const int64_t
     free(slot); free(used); free(fill); free(sample);
     return rc;
 }
+
+/* Weakly connected components (the connected components of the undirected
+ * graph underlying the arcs; for a symmetric digraph these are the connected
+ * components Algorithm 4 computes): a sequential union-find over the arcs,
+ * union by size with path compression (Tarjan 1975), then labels[v] = the
+ * smallest vertex id of v's component. */
+static int64_t wcc_find(int64_t *parent, int64_t x) {
+    int64_t r = x;
+    while (parent[r] != r) r = parent[r];
+    while (parent[x] != r) {
+        int64_t nx = parent[x];
+        parent[x] = r;
+        x = nx;
+    }
+    return r;
+}
+
+int or_wcc(int64_t n, const int32_t *off, const int32_t *adj, int32_t *labels) {
+    if (n < 0) return -1;
+    if (n == 0) return 0;
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *size = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *mn = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!parent || !size || !mn) { free(parent); free(size); free(mn); return -2; }
+    for (int64_t v = 0; v < n; v++) { parent[v] = v; size[v] = 1; }
+    for (int64_t u = 0; u < n; u++)
+        for (int64_t e = off[u]; e < off[u + 1]; e++) {
+            int64_t a = wcc_find(parent, u), b = wcc_find(parent, adj[e]);
+            if (a == b) continue;
+            if (size[a] < size[b]) { int64_t t = a; a = b; b = t; }
+            parent[b] = a;
+            size[a] += size[b];
+        }
+    for (int64_t v = 0; v < n; v++) mn[v] = (int32_t)n;
+    for (int64_t v = 0; v < n; v++) {
+        int64_t r = wcc_find(parent, v);
+        if ((int32_t)v < mn[r]) mn[r] = (int32_t)v;
+    }
+    for (int64_t v = 0; v < n; v++) labels[v] = mn[wcc_find(parent, v)];
+    free(parent); free(size); free(mn);
+    return 0;
+}
+
+/* Least-element lists (Section 5.2): with the vertices in the total order
+ * order[0..n), the list of u holds every s with d(s, u) < d(k, u) for all k
+ * before s in the order (d along arcs from s to u; on a symmetric digraph,
+ * the undirected distance the paper uses).  Computed source by source in
+ * order: a BFS from s that only enters a vertex u while d(s, u) < delta(u),
+ * the smallest distance to u from any earlier source; every vertex it enters
+ * gets (s, d) appended and delta(u) = d (Cohen's sequential construction,
+ * which Algorithm 5 batches).  Output CSR: entries of u at
+ * [off[u], off[u+1]) in order of the sources' positions, i.e. decreasing
+ * distance; src/dist hold at most cap entries, *count the total.  Returns 0,
+ * -1 bad argument, -2 out of memory, -3 cap exceeded (off still complete). */
+int or_le_lists(int64_t n, const int32_t *off, const int32_t *adj, const int32_t *order, int64_t *loff,
+                int32_t *src, int32_t *dist, int64_t cap, int64_t *count) {
+    if (n < 0 || !count || (n > 0 && (!order || !loff))) return -1;
+    *count = 0;
+    if (n == 0) { if (loff) loff[0] = 0; return 0; }
+    int32_t *delta = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    /* entries are produced source by source; keep them as (u, s, d) rows */
+    int64_t rcap = 4 * n + 16, rows = 0;
+    int32_t *ru = (int32_t *)malloc(sizeof(int32_t) * (size_t)rcap);
+    int32_t *rs = (int32_t *)malloc(sizeof(int32_t) * (size_t)rcap);
+    int32_t *rd = (int32_t *)malloc(sizeof(int32_t) * (size_t)rcap);
+    uint8_t *used = (uint8_t *)calloc((size_t)n, 1);
+    if (!delta || !d || !seen || !queue || !ru || !rs || !rd || !used) {
+        free(delta); free(d); free(seen); free(queue); free(ru); free(rs); free(rd); free(used);
+        return -2;
+    }
+    int rc = 0;
+    for (int64_t v = 0; v < n; v++) { delta[v] = INT32_MAX; seen[v] = -1; }
+    for (int64_t p = 0; p < n && rc == 0; p++) {
+        const int32_t s = order[p];
+        if (s < 0 || s >= n || used[s]) { rc = -1; break; }
+        used[s] = 1;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        seen[s] = (int32_t)p;
+        d[s] = 0;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            /* u is entered only while it improves on delta(u) */
+            if (rows == rcap) {
+                rcap *= 2;
+                int32_t *a = (int32_t *)realloc(ru, sizeof(int32_t) * (size_t)rcap);
+                int32_t *b = a ? (int32_t *)realloc(rs, sizeof(int32_t) * (size_t)rcap) : NULL;
+                int32_t *c = b ? (int32_t *)realloc(rd, sizeof(int32_t) * (size_t)rcap) : NULL;
+                if (a) ru = a;
+                if (b) rs = b;
+                if (c) rd = c;
+                if (!a || !b || !c) { rc = -2; break; }
+            }
+            ru[rows] = u; rs[rows] = s; rd[rows] = d[u]; rows++;
+            delta[u] = d[u];
+            for (int64_t e = off[u]; e < off[u + 1]; e++) {
+                const int32_t w = adj[e];
+                if (seen[w] == (int32_t)p) continue;
+                if (d[u] + 1 >= delta[w]) continue;
+                seen[w] = (int32_t)p;
+                d[w] = d[u] + 1;
+                queue[tail++] = w;
+            }
+        }
+    }
+    if (rc == 0) {
+        /* counting sort of the rows by u; within u they are already in
+         * source order (rows were produced source by source) */
+        for (int64_t v = 0; v <= n; v++) loff[v] = 0;
+        for (int64_t i = 0; i < rows; i++) loff[ru[i] + 1]++;
+        for (int64_t v = 0; v < n; v++) loff[v + 1] += loff[v];
+        *count = rows;
+        if (rows > cap) {
+            rc = -3;
+        } else {
+            int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+            if (!cur) {
+                rc = -2;
+            } else {
+                memcpy(cur, loff, sizeof(int64_t) * (size_t)n);
+                for (int64_t i = 0; i < rows; i++) {
+                    const int64_t at = cur[ru[i]]++;
+                    src[at] = rs[i];
+                    dist[at] = rd[i];
+                }
+                free(cur);
+            }
+        }
+    }
+    free(delta); free(d); free(seen); free(queue); free(ru); free(rs); free(rd); free(used);
+    return rc;
+}

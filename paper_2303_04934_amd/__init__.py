@@ -19,7 +19,7 @@ import numpy as np
 from . import _native
 from ._native import POLICY_FLOATS, STATUS_NAMES, Options, Stats
 
-__all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_labels_static", "scc_cc", "scc_reach",
+__all__ = ["SccError", "DeviceGraph", "to_device", "default_options", "scc_labels", "scc_labels_static", "scc_cc", "scc_le_lists", "scc_reach",
            "scc_labels_batched", "bag_selftest", "bag_stats", "policy_load", "policy_eval", "trace_read", "version",
            "POLICY_FLOATS", "TRACE_FIELDS"]
 
@@ -147,6 +147,34 @@ def scc_cc(dg: DeviceGraph, options: Options | None = None, return_stats: bool =
                     ctypes.byref(st))
     _check(lib, ctx, rc)
     out = out[:dg.n]
+    return (out, st.as_dict()) if return_stats else out
+
+
+def scc_le_lists(dg: DeviceGraph, options: Options | None = None, capacity: int | None = None,
+                 return_stats: bool = False):
+    """Least-element lists: (order int32[n], loff int64[n+1], src int32[k],
+    dist int32[k]) device tensors; see scc_le_lists in hipscc.h."""
+    torch = _torch()
+    lib = _native.load()
+    dev = dg.out_off.device
+    ctx = _current(dg.out_off)
+    n = dg.n
+    if capacity is None:
+        capacity = max(64, 8 * n)
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    loff = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    src = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    dist = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    cnt = ctypes.c_int64(0)
+    st = Stats()
+    g = dg.c_struct()
+    rc = lib.scc_le_lists(ctx, ctypes.byref(g), order.data_ptr(), loff.data_ptr(), src.data_ptr(), dist.data_ptr(),
+                          capacity, ctypes.byref(cnt), ctypes.byref(options) if options else None, ctypes.byref(st))
+    if rc == _native.SCC_ECAPACITY:
+        return scc_le_lists(dg, options, int(cnt.value), return_stats)
+    _check(lib, ctx, rc)
+    k = int(cnt.value)
+    out = (order[:n], loff, src[:k], dist[:k])
     return (out, st.as_dict()) if return_stats else out
 
 

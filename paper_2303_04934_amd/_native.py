@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["scc_version", "scc_default_options", "scc_create", "scc_destroy", "scc_last_error", "scc_labels",
            "scc_reach", "scc_labels_batched", "scc_policy_load", "scc_policy_eval", "scc_bag_selftest",
-           "scc_trace_read", "scc_bag_stats", "scc_labels_static", "scc_cc"]
+           "scc_trace_read", "scc_bag_stats", "scc_labels_static", "scc_cc", "scc_le_lists"]
 TRACE_FIELDS = 12
 
 _lib = None
@@ -82,6 +82,7 @@ def load():
     lib.scc_labels.argtypes = [vp, P(Graph), vp, P(Options), P(Stats)]
     lib.scc_labels_static.argtypes = [vp, P(Graph), vp, P(Options), P(Stats)]
     lib.scc_cc.argtypes = [vp, P(Graph), vp, P(Options), P(Stats)]
+    lib.scc_le_lists.argtypes = [vp, P(Graph), vp, vp, vp, vp, i64, P(i64), P(Options), P(Stats)]
     lib.scc_reach.argtypes = [vp, P(Graph), i32, vp, i32, vp, vp, i64, P(i64), P(Options), P(Stats)]
     lib.scc_labels_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, P(Options), P(Stats)]
     lib.scc_policy_load.argtypes = [vp, vp, i64]

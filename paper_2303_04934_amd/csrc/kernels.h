@@ -78,8 +78,9 @@ __device__ __forceinline__ void stripes_fold(RoundCtl *rc, LaneStripes *ls, int 
 struct Shared {
     uint32_t k;            // sources selected for the batch
     uint32_t first;        // first active permutation position (batch 1)
-    uint32_t emit;         // pairs emitted by scc_reach
+    uint32_t emit;         // pairs emitted by scc_reach (entries logged by a LE-lists batch)
     uint32_t bad;          // validation flags
+    unsigned long long cursor;  // LE-lists: entries in the list log
 };
 
 // Call-level counts that whole grids add to, striped like LaneStripes (block
@@ -109,7 +110,7 @@ constexpr int kQmask = kQcap - 1;
 constexpr int kStepArcs = 256;  // arcs a wave commits to per local-search step
 constexpr int kHeavyChunk = 4096;  // arcs per edge-parallel work item
 
-enum { kSingle = 0, kMulti = 1, kMultiFirst = 2, kLdd = 3 };
+enum { kSingle = 0, kMulti = 1, kMultiFirst = 2, kLdd = 3, kLe = 4 };
 
 // One reachability search (one direction).  kSingle claims vertices in a
 // visited bitmap whose bits were pre-set for every vertex outside the search's
@@ -118,7 +119,10 @@ enum { kSingle = 0, kMulti = 1, kMultiFirst = 2, kLdd = 3 };
 // (first[v] = source index) and only later pairs in the reach table.  kLdd
 // is kSingle for the low-diameter decomposition of Algorithm 4: an entry
 // carries its cluster centre in place of the source index, and a claim also
-// records owner[w] = centre.
+// records owner[w] = centre.  kLe is the pruned multi-BFS of Algorithm 5 (LE
+// lists): pairs in the table, but an arc (u, w) is followed at distance
+// level + 1 only while that beats delta(w) (label holds delta), and there is
+// no local search (the BFS order matters).
 struct Search {
     const int32_t *off;
     const int32_t *adj;
@@ -127,6 +131,7 @@ struct Search {
     uint64_t *table;        // kMulti
     int32_t *first;         // kMultiFirst: per-vertex first-source slot (-1 = empty)
     int32_t *owner;         // kLdd: cluster centre of each claimed vertex
+    int32_t level;          // kLe: distance of the entries this round expands
     uint64_t tmask;
     uint32_t probe_limit;
     const int32_t *srclab;  // kMulti: label of source j
@@ -554,7 +559,7 @@ __global__ void k_batch_reset(Shared *sh, RoundCtl *rc0, RoundCtl *rc1) {
 // its first reach-table probe and its offsets together.
 template <int MODE, int ILP>
 __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint32_t nblk) {
-    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst;
+    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst || MODE == kLe;
     constexpr bool FIRST = MODE == kMultiFirst;
     __shared__ uint64_t Qk[kWavesPerBlock][kQcap];                 // (vertex, source) keys
     __shared__ int2 Qr[kWavesPerBlock][kQcap];                     // (first arc, degree)
@@ -784,7 +789,8 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                     }
 #pragma unroll
                     for (int j = 0; j < ILP; j++) {
-                        st[j] = (va[j] && nlab[j] == slab[lo_[j]]) ? 2 : 0;
+                        const bool admit = MODE == kLe ? S.level + 1 < nlab[j] : nlab[j] == slab[lo_[j]];
+                        st[j] = (va[j] && admit) ? 2 : 0;
                         c_att += st[j] == 2 ? 1 : 0;
                         nr[j] = make_int2(o0[j], o1[j] - o0[j]);
                     }
@@ -944,7 +950,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(LanePair P) {
 // its four waves stride over the slice; claims go to the bag.
 template <int MODE>
 __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint32_t nblk) {
-    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst;
+    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst || MODE == kLe;
     RoundCtl *rc = S.rc;
     uint32_t nh = ld_relaxed(&rc->heavy_n[S.par]);
     if (nh == 0) return;
@@ -964,7 +970,7 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
         const int64_t d = (int64_t)S.off[u + 1] - beg0;
         const int64_t lo = (int64_t)chunk * kHeavyChunk;
         const int64_t len = (d - lo) < kHeavyChunk ? (d - lo) : kHeavyChunk;
-        const int32_t lab = PAIRS ? S.srclab[src] : 0;
+        const int32_t lab = (MODE == kMulti || MODE == kMultiFirst) ? S.srclab[src] : 0;
         if (chunk == 0 && threadIdx.x == 0) c_exp++;
         for (int64_t base = (int64_t)wv * kWave; base < len; base += kBlock) {
             const int64_t a = base + lane;
@@ -977,7 +983,7 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
                     c_att++;
                     claimed = claim_bit(S.vis, w);
                     if (MODE == kLdd && claimed) S.owner[w] = (int32_t)src;
-                } else if (S.label[w] == lab) {
+                } else if (MODE == kLe ? S.level + 1 < S.label[w] : S.label[w] == lab) {
                     c_att++;
                     const int c = MODE == kMultiFirst
                                       ? claim_pair_first(S.first, S.table, S.tmask, S.probe_limit, w, src)
@@ -1643,6 +1649,120 @@ __global__ __launch_bounds__(kBlock) void k_cc_union(int32_t n, int64_t m, const
 __global__ void k_cc_finish(int32_t n, const int32_t *owner, int32_t *parent, int32_t *label) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         label[v] = ~uf_find(parent, owner[v]);
+}
+
+// ------------------------------------------------------------ LE-lists ----
+// Least-element lists by the BGSS batches of Algorithm 5: the vertices in a
+// random order, batch i = the next 2^(i-1) of them; each batch runs a pruned
+// multi-BFS (kLe rounds) from its sources, every pair (w, j) it claims at
+// distance d < delta(w) is logged, and afterwards, per vertex, the pairs of
+// the batch are filtered against the batch's earlier sources, delta drops to
+// the best distance, and the survivors join the lists.
+
+// Sources of a batch: srcvert[j] = the vertex at position p0 + j.
+__global__ void k_le_sources(Perm P, uint32_t p0, uint32_t k, int32_t *srcvert) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x)
+        srcvert[j] = (int32_t)perm_apply(P, p0 + j);
+}
+
+__global__ void k_perm_write(Perm P, int32_t n, int32_t *order) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        order[i] = (int32_t)perm_apply(P, (uint32_t)i);
+}
+
+// Appends the frontier (the pairs first reached at distance `level`) to the
+// batch log: key (w << kbits) | j, value level.  Slots from one counter, one
+// reservation per block.
+__global__ __launch_bounds__(kBlock) void k_le_log(const uint64_t *F, const RoundCtl *rc, int par, uint64_t fcap,
+                                                   int32_t level, uint32_t kbits, uint64_t *keys, int32_t *dist,
+                                                   uint64_t cap, Shared *sh) {
+    uint64_t nf = rc->nF[par];
+    if (nf > fcap) nf = fcap;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < nf; i0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = i0 + threadIdx.x;
+        const bool h = i < nf;
+        const uint64_t m = ballot(h);
+        const uint32_t base = block_reserve(&sh->emit, (uint32_t)popc64(m));
+        if (h) {
+            const uint64_t pos = (uint64_t)base + rank_below(m);
+            if (pos < cap) {
+                const uint64_t e = F[i];
+                keys[pos] = ((uint64_t)(uint32_t)key_vertex(e) << kbits) | key_source(e);
+                dist[pos] = level;
+            }
+        }
+    }
+}
+
+// The batch log sorted by (w, j): within a vertex's run of entries (sources
+// in order), an entry survives iff its distance beats every earlier entry of
+// the run (Algorithm 5 filters the triples that violate the list's order);
+// the last survivor carries the new delta(w).  One thread walks each run.
+__global__ void k_le_filter(const uint64_t *keys, const int32_t *dist, uint64_t cnt, uint32_t kbits, uint8_t *keep,
+                            int32_t *delta) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t w = keys[i] >> kbits;
+        if (i > 0 && (keys[i - 1] >> kbits) == w) continue;  // not the start of a run
+        int32_t best = kInf32;
+        uint64_t r = i;
+        for (; r < cnt && (keys[r] >> kbits) == w; r++) {
+            const bool k = dist[r] < best;
+            keep[r] = k ? 1 : 0;
+            if (k) best = dist[r];
+        }
+        if (best < delta[w]) delta[w] = best;
+    }
+}
+
+// Survivors of a batch -> the list log: key (w << pbits) | position of the
+// source, value distance.
+__global__ __launch_bounds__(kBlock) void k_le_append(const uint64_t *keys, const int32_t *dist, const uint8_t *keep,
+                                                      uint64_t cnt, uint32_t kbits, uint32_t p0, uint32_t pbits,
+                                                      uint64_t *lkeys, int32_t *ldist, uint64_t cap,
+                                                      unsigned long long *cursor) {
+    __shared__ uint32_t part[kWavesPerBlock];
+    __shared__ unsigned long long base_s;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < cnt; i0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = i0 + threadIdx.x;
+        const bool h = i < cnt && keep[i];
+        const uint64_t m = ballot(h);
+        if (lane_id() == 0) part[threadIdx.x / kWave] = (uint32_t)popc64(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) t += part[w];
+            base_s = t ? atomicAdd(cursor, t) : 0ull;
+        }
+        __syncthreads();
+        unsigned long long b = base_s;
+        for (int w = 0; w < (int)(threadIdx.x / kWave); w++) b += part[w];
+        __syncthreads();
+        if (h) {
+            const uint64_t pos = b + rank_below(m);
+            if (pos < cap) {
+                const uint64_t w = keys[i] >> kbits;
+                const uint64_t j = keys[i] & ((1ull << kbits) - 1);
+                lkeys[pos] = (w << pbits) | (p0 + j);
+                ldist[pos] = dist[i];
+            }
+        }
+    }
+}
+
+// The sorted list log -> CSR: loff[w] = first entry of w; sources recovered
+// from their positions.
+__global__ void k_le_csr(const uint64_t *lkeys, const int32_t *ldist, uint64_t cnt, uint32_t pbits, int32_t n, Perm P,
+                         int64_t *loff, int32_t *src, int32_t *dist) {
+    const uint64_t pmask = (1ull << pbits) - 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= cnt; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t w = i < cnt ? (int64_t)(lkeys[i] >> pbits) : (int64_t)n;
+        const int64_t wp = i > 0 ? (int64_t)(lkeys[i - 1] >> pbits) : -1;
+        for (int64_t x = wp + 1; x <= w; x++) loff[x] = (int64_t)i;  // vertices without entries in between
+        if (i < cnt) {
+            src[i] = (int32_t)perm_apply(P, (uint32_t)(lkeys[i] & pmask));
+            dist[i] = ldist[i];
+        }
+    }
 }
 
 // ------------------------------------------------------------ bag test ----

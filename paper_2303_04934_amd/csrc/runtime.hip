@@ -72,7 +72,7 @@ struct scc_ctx {
     int num_cu = 256;
     uint64_t table_slots_max = 1ull << 24;  // cap of the estimated reach-table size (set from device memory)
     int expand_blocks = 2048;
-    int expand_grid[4][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
+    int expand_grid[5][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
     int arcs_per_lane = 1;          // options.arcs_per_lane of the current call
     double vgc_fill = 2.0;          // options.vgc_fill of the current call
     std::string err;
@@ -96,6 +96,11 @@ struct scc_ctx {
     DevBuf<uint64_t> rkeys[2];      // scc_reach: pair sort keys (double buffer)
     DevBuf<uint8_t> rtemp;          // scc_reach: radix sort scratch
     DevBuf<int32_t> bstart;         // scc_cc: first vertex of each arc block
+    // scc_le_lists: a batch's pair log and its sorted copy, the keep flags,
+    // the list log and its sorted copy
+    DevBuf<uint64_t> lk[2], gk[2];
+    DevBuf<int32_t> ld[2], gd[2];
+    DevBuf<uint8_t> lkeep;
     uint32_t salt = 1;
     bool tables_dirty = false;      // a failed call may leave claims behind
     // stamp/fin/sig_in/sig_out are known clean on [0, vclean_n) (zero sums,
@@ -188,6 +193,20 @@ void ensure(scc_ctx *c, DevBuf<T> &b, uint64_t n, bool *grew = nullptr) {
     }
     b.cap = want;
     if (grew) *grew = true;
+}
+
+// Grows b to at least n elements keeping its first `keep` elements.
+template <typename T>
+void grow_keep(scc_ctx *c, DevBuf<T> &b, uint64_t n, uint64_t keep) {
+    if (b.cap >= n) return;
+    DevBuf<T> nb;
+    ensure(c, nb, n);
+    if (keep > 0 && b.p)
+        HIPCHK(hipMemcpyAsync(nb.p, b.p, sizeof(T) * std::min<uint64_t>(keep, b.cap), hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (b.p) HIPCHK(hipFree(b.p));
+    b = nb;
 }
 
 template <typename T>
@@ -289,6 +308,7 @@ scc_options_t defaults() {
     o.seeds_per_wave = 0;
     o.timing = 0;
     o.ldd_beta = 1.2f;
+    o.first_slot = 1;
     return o;
 }
 
@@ -396,7 +416,7 @@ Search make_search(scc_ctx *c, int id, const scc_options_t &o, int mode) {
     S.rc = &c->dctl->lane[id];
     S.ls = &c->dctl->ls[id];
     S.cn = &c->dctl->cn;
-    S.kind = (mode == kMulti || mode == kMultiFirst) ? kKindExpandMulti : kKindExpandSingle;
+    S.kind = (mode == kMulti || mode == kMultiFirst || mode == kLe) ? kKindExpandMulti : kKindExpandSingle;
     S.tau = o.tau;
     S.seeds = o.seeds_per_wave;
     S.heavy_deg = 1024;
@@ -508,6 +528,11 @@ void timed_collect(scc_ctx *c) {
 
 // The expand kernel of a search mode and arcs-per-lane setting.
 const void *expand_kernel(int mode, int apl) {
+    if (mode == kLe) {
+        if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kLe, 1>);
+        if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kLe, 2>);
+        return reinterpret_cast<const void *>(&k_expand<kLe, 4>);
+    }
     if (mode == kLdd) {
         if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kLdd, 1>);
         if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kLdd, 2>);
@@ -559,9 +584,10 @@ void launch_sparse(scc_ctx *c, Lane **ls, int nl) {
     HIPCHK(hipLaunchKernel(fn, dim3(eb), dim3(kBlock), args, 0, c->stream));
     timed_end(c, t);
     P.split = hb / 2;
-    const bool pairs = mode == kMulti || mode == kMultiFirst;
+    const bool pairs = mode == kMulti || mode == kMultiFirst || mode == kLe;
     const int th = timed_begin(c, pairs ? SCC_KERNEL_HEAVY_MULTI : SCC_KERNEL_HEAVY_SINGLE);
-    if (mode == kLdd) hipLaunchKernelGGL(k_expand_heavy<kLdd>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    if (mode == kLe) hipLaunchKernelGGL(k_expand_heavy<kLe>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    else if (mode == kLdd) hipLaunchKernelGGL(k_expand_heavy<kLdd>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else if (mode == kMultiFirst) hipLaunchKernelGGL(k_expand_heavy<kMultiFirst>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3(hb), dim3(kBlock), 0, c->stream, P);
@@ -1600,7 +1626,7 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
         // one resident wave of blocks per expand variant: its waves take the
         // frontier's groups statically, so blocks beyond the resident set
         // would run a second, serial local search
-        for (int m = 0; m < 4; m++)
+        for (int m = 0; m < 5; m++)
             for (int ai = 0; ai < 3; ai++) {
                 int b = 0;
                 HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, expand_kernel(m, 1 << ai), kBlock, 0));
@@ -1639,6 +1665,8 @@ void scc_destroy(scc_ctx_t *c) {
     release(c->Tout); release(c->Tin); release(c->ubuf);
     release(c->firstS[0]); release(c->firstS[1]);
     release(c->rkeys[0]); release(c->rkeys[1]); release(c->rtemp); release(c->bstart);
+    for (int i = 0; i < 2; i++) { release(c->lk[i]); release(c->gk[i]); release(c->ld[i]); release(c->gd[i]); }
+    release(c->lkeep);
     policy_release(c->policy);
     if (c->dctl) (void)hipFree(c->dctl);
     if (c->hctl) (void)hipHostFree(c->hctl);
@@ -2071,6 +2099,224 @@ scc_status scc_cc(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, const
             stats->rounds_first = rounds;
             stats->batches = rounds + 1;
             stats->n_scc = count_sum(c, &CountLine::nscc);
+            fill_counters(c, stats, n);
+            stats->ms_total = now_ms() - t0;
+        }
+    });
+}
+
+scc_status scc_le_lists(scc_ctx_t *c, const scc_graph_t *g, int32_t *order_out, int64_t *loff, int32_t *src_out,
+                        int32_t *dist_out, int64_t capacity, int64_t *n_entries, const scc_options_t *opt,
+                        scc_stats_t *stats) {
+    return guard(c, [&] {
+        if (n_entries) *n_entries = 0;
+        if (!g || !n_entries) { set_err(c, "graph or n_entries is NULL"); throw Fail{SCC_EINVAL}; }
+        if (g->n < 0 || g->m < 0 || capacity < 0) { set_err(c, "negative n, m or capacity"); throw Fail{SCC_EINVAL}; }
+        if (!g->out_off || (g->m > 0 && !g->out_adj)) { set_err(c, "graph has a NULL out array"); throw Fail{SCC_EINVAL}; }
+        if (!loff || (capacity > 0 && (!src_out || !dist_out))) { set_err(c, "output array is NULL"); throw Fail{SCC_EINVAL}; }
+        scc_options_t o = opt ? *opt : defaults();
+        check_opts(c, o);
+        const double t0 = now_ms();
+        init_call(c, stats, g->n, g->m, &o);
+        const int32_t n = g->n;
+        if (n == 0) {
+            fill_u32(c, (uint32_t *)loff, 2, 0u);
+            HIPCHK(hipStreamSynchronize(c->stream));
+            return;
+        }
+        const bool ph = stats != nullptr;
+        ensure_vertex_state(c, n);
+        c->tables_dirty = true;  // the batches leave their pairs in the table
+        if (o.validate) {
+            uint32_t *bad = &c->dctl->sh.bad;
+            fill_u32(c, bad, 1, 0u);
+            hipLaunchKernelGGL(k_validate_off, dim3(grid_for(c, (uint64_t)n + 1)), dim3(kBlock), 0, c->stream, n,
+                               g->m, g->out_off, bad);
+            if (g->m > 0)
+                hipLaunchKernelGGL(k_validate_adj, dim3(grid_for(c, (uint64_t)g->m)), dim3(kBlock), 0, c->stream, n,
+                                   g->m, g->out_adj, (int32_t *)nullptr, bad);
+            LAUNCHCHK("k_validate_*");
+            sync_ctl(c);
+            if (c->hctl->sh.bad) { set_err(c, "invalid CSR (offsets or arc targets)"); throw Fail{SCC_EGRAPH}; }
+        }
+        // delta(v): the best distance to v from the sources of earlier batches
+        int32_t *delta = c->label.p;
+        fill_u32(c, (uint32_t *)delta, (uint64_t)n, (uint32_t)kInf32);
+        Perm P;
+        P.n = (uint32_t)n;
+        uint32_t bits = 1;
+        while ((1ull << (2 * bits)) < (uint64_t)n) bits++;
+        P.half_bits = bits;
+        P.key = mix64(o.seed ^ 0x13198A2E03707344ull);
+        if (order_out) {
+            hipLaunchKernelGGL(k_perm_write, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, P, n, order_out);
+            LAUNCHCHK("k_perm_write");
+        }
+        uint32_t pbits = 1;
+        while ((1ll << pbits) < (int64_t)n) pbits++;
+        Shared *sh = &c->dctl->sh;
+        uint64_t gcap = 4 * (uint64_t)n + 1024;  // the list log: about n H_n entries expected
+        ensure(c, c->gk[0], gcap);
+        ensure(c, c->gd[0], gcap);
+        gcap = std::min<uint64_t>(c->gk[0].cap, c->gd[0].cap);
+        fill_u32(c, (uint32_t *)&sh->cursor, 2, 0u);
+        uint64_t total = 0;
+        uint64_t pos = 0;
+        double bsize = 1.0;
+        uint64_t prev_pairs = 0, prev_k = 1;
+        int64_t levels = 0, batches = 0, restarts = 0;
+        phase_begin(c, 2, ph);
+        while (pos < (uint64_t)n) {
+            const uint64_t k = std::min<uint64_t>((uint64_t)n - pos, std::max<uint64_t>((uint64_t)std::ceil(bsize - 1e-9), 1));
+            uint32_t kbits = 0;
+            while ((1ull << kbits) < k) kbits++;
+            hipLaunchKernelGGL(k_le_sources, dim3(grid_for(c, k)), dim3(kBlock), 0, c->stream, P, (uint32_t)pos,
+                               (uint32_t)k, c->srcvert.p);
+            LAUNCHCHK("k_le_sources");
+            // table for the batch's pairs: the previous batch's pairs scaled by
+            // the growth (a larger table on overflow)
+            uint64_t ts = next_pow2(std::min<uint64_t>(
+                std::max<uint64_t>({1024, 4 * k, 2 * prev_pairs * ((k + prev_k - 1) / prev_k)}), c->table_slots_max));
+            uint64_t logged = 0;
+            for (;;) {
+                bool grew = false;
+                ensure(c, c->Tout, ts, &grew);
+                fill_u64(c, c->Tout.p, grew ? c->Tout.cap : ts, kEmpty64);
+                ensure_lane(c, 0, std::max<uint64_t>(ts, (uint64_t)n), lam_log2_for(o, (uint64_t)n));
+                reset_bag(c, 0);
+                reset_lane_ctl(c, 0);
+                ensure(c, c->lk[0], ts);
+                ensure(c, c->ld[0], ts);
+                const uint64_t lcap = std::min<uint64_t>(c->lk[0].cap, c->ld[0].cap);
+                fill_u32(c, &sh->emit, 1, 0u);
+                fill_u32(c, &sh->k, 1, (uint32_t)k);
+                Lane L;
+                L.id = 0;
+                L.mode = kLe;
+                L.n = n;
+                L.S = make_search(c, 0, o, kLe);
+                L.S.off = g->out_off;
+                L.S.adj = g->out_adj;
+                L.S.label = delta;
+                L.S.table = c->Tout.p;
+                L.S.tmask = ts - 1;
+                L.S.tau = 0;  // BFS order: no local search
+                L.avg_deg = std::max(1.0, (double)g->m / (double)n);
+                L.par = 0;
+                SeedArgs SA;
+                memset(&SA, 0, sizeof SA);
+                SA.T[0] = c->Tout.p;
+                SA.mask[0] = ts - 1;
+                SA.F[0] = c->F[0].p;
+                SA.rc[0] = &c->dctl->lane[0];
+                SA.ls[0] = &c->dctl->ls[0];
+                hipLaunchKernelGGL(k_seed_multi, dim3(grid_for(c, k), 1), dim3(kBlock), 0, c->stream, c->srcvert.p, sh,
+                                   SA, kProbeLimit);
+                LAUNCHCHK("k_seed_multi");
+                hipLaunchKernelGGL(k_le_log, dim3(grid_for(c, k)), dim3(kBlock), 0, c->stream, L.S.F, L.S.rc, 0,
+                                   L.S.fcap, 0, kbits, c->lk[0].p, c->ld[0].p, lcap, sh);
+                LAUNCHCHK("k_le_log");
+                int32_t level = 0;
+                int K = 1;
+                bool failed = false;
+                for (;;) {
+                    for (int r = 0; r < K; r++) {
+                        L.S.level = level;
+                        Lane *one = &L;
+                        launch_sparse(c, &one, 1);
+                        hipLaunchKernelGGL(k_le_log, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, L.S.F,
+                                           L.S.rc, L.par, L.S.fcap, level + 1, kbits, c->lk[0].p, c->ld[0].p, lcap, sh);
+                        LAUNCHCHK("k_le_log");
+                        level++;
+                    }
+                    sync_ctl(c);
+                    timed_collect(c);
+                    const RoundCtl &rc = c->hctl->lane[0];
+                    if ((rc.err & (kErrTable | kErrCapacity)) || c->hctl->bag[0].overflow ||
+                        (uint64_t)c->hctl->sh.emit > lcap) {
+                        failed = true;
+                        break;
+                    }
+                    if (rc.nF[0] + rc.nF[1] == 0) break;
+                    K = std::min(K * 2, kMaxSlots);
+                }
+                levels += c->hctl->lane[0].rounds;
+                if (!failed) {
+                    logged = c->hctl->sh.emit;
+                    break;
+                }
+                // the batch restarts on a table (and log) twice as large; delta
+                // has not changed yet
+                restarts++;
+                ts *= 2;
+            }
+            // per vertex: sort the batch's pairs by (w, j), keep those that beat
+            // every earlier source of the batch, lower delta, append to the lists
+            if (logged > 0) {
+                ensure(c, c->lk[1], logged);
+                ensure(c, c->ld[1], logged);
+                ensure(c, c->lkeep, logged);
+                const uint32_t wbits = pbits + 1;
+                size_t tb = 0;
+                HIPCHK(rocprim::radix_sort_pairs(nullptr, tb, c->lk[0].p, c->lk[1].p, c->ld[0].p, c->ld[1].p, logged, 0u,
+                                                 kbits + wbits, c->stream));
+                ensure(c, c->rtemp, (uint64_t)tb);
+                HIPCHK(rocprim::radix_sort_pairs((void *)c->rtemp.p, tb, c->lk[0].p, c->lk[1].p, c->ld[0].p, c->ld[1].p,
+                                                 logged, 0u, kbits + wbits, c->stream));
+                hipLaunchKernelGGL(k_le_filter, dim3(grid_for(c, logged)), dim3(kBlock), 0, c->stream, c->lk[1].p,
+                                   c->ld[1].p, logged, kbits, c->lkeep.p, delta);
+                LAUNCHCHK("k_le_filter");
+                // room for every survivor of this batch in the list log
+                if (total + logged > gcap) {
+                    const uint64_t want = std::max<uint64_t>(2 * gcap, total + logged);
+                    grow_keep(c, c->gk[0], want, total);
+                    grow_keep(c, c->gd[0], want, total);
+                    gcap = std::min<uint64_t>(c->gk[0].cap, c->gd[0].cap);
+                }
+                hipLaunchKernelGGL(k_le_append, dim3(grid_for(c, logged)), dim3(kBlock), 0, c->stream, c->lk[1].p,
+                                   c->ld[1].p, c->lkeep.p, logged, kbits, (uint32_t)pos, pbits, c->gk[0].p, c->gd[0].p,
+                                   gcap, &sh->cursor);
+                LAUNCHCHK("k_le_append");
+                sync_ctl(c);
+                total = c->hctl->sh.cursor;
+            }
+            prev_pairs = logged;
+            prev_k = k;
+            pos += k;
+            bsize *= (double)o.beta;
+            batches++;
+        }
+        phase_end(c, ph);
+        *n_entries = (int64_t)total;
+        if ((int64_t)total > capacity) {
+            set_err(c, "%llu list entries exceed capacity %lld", (unsigned long long)total, (long long)capacity);
+            throw Fail{SCC_ECAPACITY};
+        }
+        // the lists: sort the log by (vertex, source position), then CSR
+        phase_begin(c, 4, ph);
+        ensure(c, c->gk[1], std::max<uint64_t>(total, 1));
+        ensure(c, c->gd[1], std::max<uint64_t>(total, 1));
+        if (total > 0) {
+            size_t tb = 0;
+            HIPCHK(rocprim::radix_sort_pairs(nullptr, tb, c->gk[0].p, c->gk[1].p, c->gd[0].p, c->gd[1].p, total, 0u,
+                                             2 * pbits + 1, c->stream));
+            ensure(c, c->rtemp, (uint64_t)tb);
+            HIPCHK(rocprim::radix_sort_pairs((void *)c->rtemp.p, tb, c->gk[0].p, c->gk[1].p, c->gd[0].p, c->gd[1].p,
+                                             total, 0u, 2 * pbits + 1, c->stream));
+        }
+        hipLaunchKernelGGL(k_le_csr, dim3(grid_for(c, total + 1)), dim3(kBlock), 0, c->stream, c->gk[1].p, c->gd[1].p,
+                           total, pbits, n, P, loff, src_out, dist_out);
+        LAUNCHCHK("k_le_csr");
+        phase_end(c, ph);
+        sync_ctl(c, stats != nullptr);
+        if (stats) {
+            double ms[kPhases] = {0, 0, 0, 0, 0};
+            phase_collect(c, ms);
+            stats->ms_multi = ms[2];
+            stats->ms_label = ms[4];
+            stats->batches = batches;
+            stats->rounds_multi = levels;
+            stats->table_restarts = restarts;
             fill_counters(c, stats, n);
             stats->ms_total = now_ms() - t0;
         }

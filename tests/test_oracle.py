@@ -423,3 +423,84 @@ def test_hashbag_load_pin_catches_a_wrong_sample_rate():
     sim = oracle.hashbag_sim([np.arange(200000)], lam_log2=10, sigma=50, alpha=0.97, kappa=1 << 20, seed=3)
     loads = [ld for _, ld, cause in sim["advances"] if cause == 0]
     assert loads and max(loads) > 0.75
+
+
+# ------------------------------------------------------ connected components ----
+def test_wcc_vs_scipy_and_symmetric_scc():
+    rng = np.random.default_rng(21)
+    for t in range(30):
+        n = int(rng.integers(1, 3000))
+        g = graphgen.random_digraph(n, float(rng.choice([0.3, 0.8, 1.5])), seed=9100 + t)
+        got = oracle.wcc_labels(g.n, g.out_off, g.out_adj)
+        A = sp.csr_matrix((np.ones(g.m), g.out_adj, g.out_off), shape=(g.n, g.n))
+        _, comp = connected_components(A, directed=True, connection="weak")
+        mins = np.full(comp.max() + 1, g.n)
+        np.minimum.at(mins, comp, np.arange(g.n))
+        assert np.array_equal(got, mins[comp])
+        # symmetrised: its SCCs (Tarjan) are its connected components
+        src = np.repeat(np.arange(g.n), np.diff(g.out_off)).astype(np.int32)
+        sym = graphgen.from_arcs(g.n, np.concatenate([src, g.out_adj]), np.concatenate([g.out_adj, src]), dedup=True)
+        assert np.array_equal(oracle.wcc_labels(sym.n, sym.out_off, sym.out_adj), oracle.scc_graph(sym))
+
+
+def test_wcc_closed_forms():
+    n = 500
+    path = csr_of(n, [(i, i + 1) for i in range(n - 1)])
+    assert (oracle.wcc_labels(n, path.out_off, path.out_adj) == 0).all()
+    g = csr_of(6, [(5, 4), (2, 3)])
+    assert list(oracle.wcc_labels(6, g.out_off, g.out_adj)) == [0, 1, 2, 2, 4, 4]
+    assert len(oracle.wcc_labels(0, np.zeros(1, np.int32), np.zeros(0, np.int32))) == 0
+
+
+# ----------------------------------------------------------------- LE-lists ----
+def _le_by_definition(g, order):
+    """u's list: walk the order, keep s when d(s, u) beats every earlier source."""
+    from scipy.sparse.csgraph import shortest_path
+    A = sp.csr_matrix((np.ones(g.m), g.out_adj, g.out_off), shape=(g.n, g.n))
+    D = shortest_path(A, method="D", directed=True, unweighted=True)  # D[s, u]
+    lists = []
+    for u in range(g.n):
+        best = np.inf
+        row = []
+        for s in order:
+            if D[s, u] < best:
+                best = D[s, u]
+                row.append((int(s), int(D[s, u])))
+        lists.append(row)
+    return lists
+
+
+def _le_rows(loff, src, dist, n):
+    return [list(zip(src[loff[u]:loff[u + 1]].tolist(), dist[loff[u]:loff[u + 1]].tolist())) for u in range(n)]
+
+
+def test_le_lists_vs_definition():
+    rng = np.random.default_rng(23)
+    for t in range(60):
+        n = int(rng.integers(1, 90))
+        g = graphgen.random_digraph(n, float(rng.choice([0.7, 1.5, 3.0])), seed=9300 + t)
+        if t % 2:
+            g = graphgen.symmetrize(g)
+        order = rng.permutation(n).astype(np.int32)
+        loff, src, dist = oracle.le_lists(g.n, g.out_off, g.out_adj, order)
+        assert _le_rows(loff, src, dist, g.n) == _le_by_definition(g, order)
+
+
+def test_le_lists_closed_forms():
+    # undirected path in natural order: L(u) = 0, 1, ..., u at distances u, ..., 0
+    n = 200
+    g = graphgen.symmetrize(csr_of(n, [(i, i + 1) for i in range(n - 1)]))
+    loff, src, dist = oracle.le_lists(n, g.out_off, g.out_adj, np.arange(n, dtype=np.int32))
+    rows = _le_rows(loff, src, dist, n)
+    for u in range(n):
+        assert rows[u] == [(s, u - s) for s in range(u + 1)]
+    # every list ends with the vertex itself at distance 0; the first vertex of
+    # the order heads the list of everything it reaches
+    h = graphgen.symmetrize(graphgen.torus(20, 20, 0.6, seed=3))
+    order = np.random.default_rng(2).permutation(h.n).astype(np.int32)
+    loff, src, dist = oracle.le_lists(h.n, h.out_off, h.out_adj, order)
+    reach0 = set(oracle.reach_pairs(h.n, h.out_off, h.out_adj, np.zeros(h.n, np.int32), [order[0]])[:, 0].tolist())
+    for u in range(h.n):
+        assert src[loff[u + 1] - 1] == u and dist[loff[u + 1] - 1] == 0
+        assert (src[loff[u]] == order[0]) == (u in reach0)
+        assert np.all(np.diff(dist[loff[u]:loff[u + 1]]) < 0)
