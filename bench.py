@@ -52,11 +52,21 @@ WORKLOADS = {
 }
 DEFAULT_WORKLOAD = "batched4096"
 BATCH_G, BATCH_LO, BATCH_SEED = 4096, 3.0, 1004
-# the frontier kernels timed with options.timing, as rocprofv3 names them
-KERNEL_NAMES = ["hipscc::k_expand<0, 1>", "hipscc::k_expand<1, 1>", "hipscc::k_pull", "hipscc::k_expand_heavy<0>",
-                "hipscc::k_expand_heavy<1>", "hipscc::k_bag_extract"]
-KERNEL_SHORT = ["k_expand0", "k_expand1", "k_pull", "k_heavy0", "k_heavy1", "k_extract"]
-NK = len(KERNEL_NAMES)
+# the frontier kernels timed with options.timing (SCC_KERNEL_* in hipscc.h)
+KERNEL_SHORT = ["k_expand0", "k_expand1", "k_pull", "k_heavy0", "k_heavy1", "k_extract", "k_union"]
+NK = len(KERNEL_SHORT)
+
+
+def kernel_name(kind, app="scc", first_slot=1):
+    """rocprofv3's name of the kernel that timing kind `kind` brackets: the
+    expand and edge-parallel kernels are instantiated per search mode (0
+    single source, 1 multi-source, 2 multi-source with first-source slots,
+    3 LDD of connectivity, 4 LE-lists BFS)."""
+    single = {"scc": 0, "cc": 3, "le": 0}[app]
+    multi = {"scc": 2 if first_slot else 1, "cc": 1, "le": 4}[app]
+    return ["hipscc::k_expand<%d, 1>" % single, "hipscc::k_expand<%d, 1>" % multi, "hipscc::k_pull",
+            "hipscc::k_expand_heavy<%d>" % single, "hipscc::k_expand_heavy<%d>" % multi, "hipscc::k_bag_extract",
+            "hipscc::k_cc_union"][kind]
 CPU_POOL = 16  # host threads for the multicore oracle (the CPU share of one GPU)
 
 
@@ -159,13 +169,13 @@ def cpu_baseline_batched(n_of, oo, oa, vb, ab, runs=3):
                     "host": host_info()}
 
 
-def roofline(ms_k, launches_k, bytes_k, dom, workload):
+def roofline(ms_k, launches_k, bytes_k, dom, workload, name):
     if launches_k[dom] <= 0 or ms_k[dom] <= 0:
         return None
     per_launch_ms = ms_k[dom] / launches_k[dom]
     per_launch_bytes = bytes_k[dom] / launches_k[dom]
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(workload, dom),
             "avg_launch_ms": per_launch_ms, "alg_bytes_per_launch": per_launch_bytes}
 
@@ -206,6 +216,7 @@ def run_batched(args, desc):
         opts = scc.default_options(validate=0)
         tau, beta, beta_fast, policy = args.schedule.split(",")
         opts.tau, opts.beta, opts.beta_fast, opts.policy = int(tau), float(beta), float(beta_fast), int(policy)
+        opts.graph_rounds = args.graph_rounds
         tuned = {"given": args.schedule}
     else:
         opts, tuned = autotune.tune(vb, ab, *arrs, base_options=base)
@@ -218,7 +229,7 @@ def run_batched(args, desc):
         _, st = scc.scc_labels_batched(vb, ab, *arrs, options=opts, return_stats=True)
     dom = max(range(NK), key=lambda i: st["ms_kernel"][i])
     probe_ms = list(st["ms_kernel"])
-    opts.timing = 1 << dom
+    opts.timing = 0 if args.graph_rounds else 1 << dom
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
@@ -280,7 +291,7 @@ def run_batched(args, desc):
     ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
     la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
     by_k = [sum(s["bytes_kernel"][i] for s in stats) for i in range(NK)]
-    rf = roofline(ms_k, la_k, by_k, dom, "batched4096")
+    rf = roofline(ms_k, la_k, by_k, dom, "batched4096", kernel_name(dom, "scc", opts.first_slot))
     if rf:
         rf["launches_per_step"] = la_k[dom] / args.steps
         rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)
@@ -319,6 +330,7 @@ def run_single(args, cfg, desc):
     if args.first_slot >= 0:
         opts.first_slot = args.first_slot
     opts.vgc_measure = args.vgc_measure
+    opts.graph_rounds = args.graph_rounds
     if args.policy == 1:
         load_policy(scc)
     # Untimed warm-up.  Its last call times every frontier kernel to find the
@@ -329,9 +341,11 @@ def run_single(args, cfg, desc):
         _, st = scc.scc_labels(dg, opts, out=out, return_stats=True)
     dom = max(range(NK), key=lambda i: st["ms_kernel"][i])
     probe_ms = list(st["ms_kernel"])
-    opts.timing = 1 << dom
+    # (captured round blocks record no per-kernel events: an A/B run of them
+    # times whole calls only)
+    opts.timing = 0 if args.graph_rounds else 1 << dom
     torch.cuda.synchronize()
-    log("warmup done; dominant frontier kernel %s" % KERNEL_NAMES[dom])
+    log("warmup done; dominant frontier kernel %s" % kernel_name(dom, "scc", opts.first_slot))
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -348,12 +362,13 @@ def run_single(args, cfg, desc):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": g.n, "m": g.m, "seed": 1000 + cfg,
                    "tau": opts.tau, "policy": "learned" if args.policy == 1 else "fixed",
-                   "first_slot": opts.first_slot, "vgc_measure": opts.vgc_measure, "shrink": args.shrink},
+                   "first_slot": opts.first_slot, "vgc_measure": opts.vgc_measure,
+                   "graph_rounds": opts.graph_rounds, "shrink": args.shrink},
     }
     ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
     la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
     by_k = [sum(s["bytes_kernel"][i] for s in stats) for i in range(NK)]
-    rf = roofline(ms_k, la_k, by_k, dom, args.workload)
+    rf = roofline(ms_k, la_k, by_k, dom, args.workload, kernel_name(dom, "scc", opts.first_slot))
     if rf:
         rf["launches_per_step"] = la_k[dom] / args.steps
         rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)
@@ -375,6 +390,85 @@ def run_single(args, cfg, desc):
         sys.exit(1)
 
 
+def run_app(args, cfg, desc):
+    """Connectivity (Algorithm 4) or LE-lists (Algorithm 5) on the symmetrised
+    workload graph: one step = one scc_cc / scc_le_lists call."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import oracle
+    import paper_2303_04934_amd as scc
+
+    t0 = time.perf_counter()
+    g = graphgen.symmetrize(graphgen.config(cfg, shrink=args.shrink))
+    log("generated %s (symmetrised) n=%d m=%d in %.1f s" % (args.workload, g.n, g.m, time.perf_counter() - t0))
+    dg = scc.to_device(g, "cuda:0")
+    opts = scc.default_options(validate=0)
+    if args.tau:
+        opts.tau = args.tau
+
+    def call(o):
+        if args.app == "cc":
+            return scc.scc_cc(dg, o, return_stats=True)
+        return scc.scc_le_lists(dg, o, return_stats=True)
+    for i in range(max(args.warmup, 1)):
+        opts.timing = (1 << NK) - 1 if i == max(args.warmup, 1) - 1 else 0
+        _, st = call(opts)
+    dom = max(range(NK), key=lambda i: st["ms_kernel"][i])
+    probe_ms = list(st["ms_kernel"])
+    opts.timing = 1 << dom
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, st = call(opts)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    log("timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3))
+    line = {
+        "metric": METRIC, "value": g.m / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "%s_%s_sym" % (args.app, args.workload), "app": args.app,
+                   "description": "symmetrised " + desc, "n": g.n, "m": g.m, "shrink": args.shrink,
+                   "tau": opts.tau, "ldd_beta": opts.ldd_beta, "beta": opts.beta},
+    }
+    ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
+    la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
+    by_k = [sum(s["bytes_kernel"][i] for s in stats) for i in range(NK)]
+    rf = roofline(ms_k, la_k, by_k, dom, "%s_%s_sym" % (args.app, args.workload), kernel_name(dom, args.app))
+    if rf:
+        rf["launches_per_step"] = la_k[dom] / args.steps
+        rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)
+        line["roofline"] = rf
+    last = stats[-1]
+    line["stats"] = {k: last[k] for k in ("ms_first", "ms_multi", "ms_label", "batches", "rounds_first",
+                                         "rounds_multi", "n_scc", "arcs_scanned", "claims", "bag_inserts",
+                                         "table_restarts", "bytes_alg")}
+    line["stats"]["kernel_ms_warmup_call"] = {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        if args.app == "cc":
+            want = oracle.wcc_labels(g.n, g.out_off, g.out_adj)
+            ok = bool(np.array_equal(res.cpu().numpy(), want))
+        else:
+            order, loff, src, dist = (x.cpu().numpy() for x in res)
+            wl, ws, wd = oracle.le_lists(g.n, g.out_off, g.out_adj, order)
+            ok = bool(np.array_equal(loff, wl) and np.array_equal(src, ws) and np.array_equal(dist, wd))
+            line["stats"]["list_entries"] = int(len(ws))
+        t = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": g.m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                                "sample": "whole graph, one run of the sequential oracle (%s), %.2f s"
+                                          % ("union-find" if args.app == "cc" else "source-by-source pruned BFS", t),
+                                "host": host_info()}
+        line["parity"] = "bit-exact vs oracle" if ok else "MISMATCH vs oracle"
+    print(json.dumps(line), flush=True)
+    if line.get("parity", "").startswith("MISMATCH"):
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,11 +476,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--shrink", type=int, default=0, help="reduce n by 2**shrink (exploration only)")
+    ap.add_argument("--app", default="scc", choices=["scc", "cc", "le"],
+                    help="scc (default), or connectivity / LE-lists on the symmetrised workload graph")
     ap.add_argument("--tau", type=int, default=0, help="VGC budget (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--policy", type=int, default=0, help="0 fixed budget, 1 learned per-round policy")
     ap.add_argument("--first-slot", type=int, default=-1, help="options.first_slot (-1: the library default)")
     ap.add_argument("--vgc-measure", type=int, default=0, help="options.vgc_measure (0 arcs, 1 claims)")
+    ap.add_argument("--graph-rounds", type=int, default=0, help="options.graph_rounds (captured round blocks)")
     ap.add_argument("--batch-hi", type=float, default=6.0,
                     help="batched workload: vertex counts log-uniform in [1e3, 10**batch_hi]")
     ap.add_argument("--schedule", default="", help="batched: tau,beta,beta_fast,policy instead of autotuning")
@@ -409,7 +506,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     cfg, desc = WORKLOADS[args.workload]
-    if args.workload == "batched4096":
+    if args.app != "scc":
+        if args.workload == "batched4096":
+            print("--app %s runs on a single-graph workload" % args.app, file=sys.stderr)
+            sys.exit(2)
+        run_app(args, cfg, desc)
+    elif args.workload == "batched4096":
         run_batched(args, desc)
     else:
         run_single(args, cfg, desc)

@@ -141,7 +141,13 @@ typedef struct {
  *                1 = new claims (generated reachability pairs, or visited
  *                vertices for a single source).
  *   ldd_beta     scc_cc: growth of the centre batches of the low-diameter
- *                decomposition per round (Section 5.1 uses 1.2; default). */
+ *                decomposition per round (Section 5.1 uses 1.2; default).
+ *   graph_rounds 1 = a block of sparse rounds between two host checks runs
+ *                as one captured HIP graph, replayed when a block with the
+ *                same round count and launch arguments comes again (cached
+ *                per context); 0 (default) = one launch per kernel.  Not
+ *                with timing, trace or the learned policy, and ignored by
+ *                scc_labels_static. */
 typedef struct {
     int32_t tau;
     float beta;
@@ -166,6 +172,7 @@ typedef struct {
     int32_t first_slot;
     int32_t vgc_measure;
     float ldd_beta;
+    int32_t graph_rounds;
 } scc_options_t;
 
 /* Frontier kernels timed with options.timing. */
@@ -175,7 +182,8 @@ typedef struct {
 #define SCC_KERNEL_HEAVY_SINGLE 3   /* edge-parallel pass, single-source lanes */
 #define SCC_KERNEL_HEAVY_MULTI 4    /* edge-parallel pass, multi-source lanes */
 #define SCC_KERNEL_EXTRACT 5        /* ExtractAll */
-#define SCC_KERNELS 6
+#define SCC_KERNEL_UNION 6          /* scc_cc: the union-find pass over the arcs */
+#define SCC_KERNELS 7
 
 /* Per-call statistics (host struct, written when non-NULL).  Times are
  * milliseconds measured with HIP events on the context's stream.  The five
@@ -209,7 +217,9 @@ typedef struct {
      * 8 (multi) or 4 (single) per claim, 8 per bag insert.  Pull: visited and
      * next words (n/4), offsets 8 per unvisited vertex, 8 per scanned arc
      * (target id + frontier word).  ExtractAll: 24 per extracted entry (bag
-     * slot read, frontier write, the entry's offsets for the degree sum). */
+     * slot read, frontier write, the entry's offsets for the degree sum).
+     * Union pass: 8 per arc (target id + its cluster), 12 per vertex
+     * (offsets, cluster), 16 per link attempt (two finds' first parents). */
     double ms_kernel[SCC_KERNELS];
     int64_t launches_kernel[SCC_KERNELS];
     int64_t bytes_kernel[SCC_KERNELS];

@@ -21,7 +21,8 @@ class Graph(ctypes.Structure):
 
 
 # frontier kernels timed with options.timing (SCC_KERNEL_* in hipscc.h)
-KERNEL_NAMES = ["k_expand<0, 1>", "k_expand<1, 1>", "k_pull", "k_expand_heavy<0>", "k_expand_heavy<1>", "k_bag_extract"]
+KERNEL_NAMES = ["k_expand<0, 1>", "k_expand<1, 1>", "k_pull", "k_expand_heavy<0>", "k_expand_heavy<1>", "k_bag_extract",
+                "k_cc_union"]
 KERNELS = len(KERNEL_NAMES)
 
 
@@ -33,7 +34,8 @@ class Options(ctypes.Structure):
                 ("seeds_per_wave", ctypes.c_int32), ("timing", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float),
                 ("beta_fast", ctypes.c_float), ("table_floor", ctypes.c_float), ("union_arcs_max", ctypes.c_int32),
-                ("first_slot", ctypes.c_int32), ("vgc_measure", ctypes.c_int32), ("ldd_beta", ctypes.c_float)]
+                ("first_slot", ctypes.c_int32), ("vgc_measure", ctypes.c_int32), ("ldd_beta", ctypes.c_float),
+                ("graph_rounds", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -11,7 +11,8 @@ enum { kCtrSeeds = 0, kCtrExpanded, kCtrArcs, kCtrAttempts, kCtrClaims, kCtrInse
 constexpr int kCtrStripes = 32;
 // Counter kinds: the work of each frontier kernel (expand single-source,
 // expand multi-source, pull, edge-parallel single- and multi-source).
-enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavySingle = 3, kKindHeavyMulti = 4, kNumKinds = 5 };
+enum { kKindExpandSingle = 0, kKindExpandMulti = 1, kKindPull = 2, kKindHeavySingle = 3, kKindHeavyMulti = 4,
+       kKindUnion = 5, kNumKinds = 6 };
 
 // Round control of one search lane (one direction of a search), in device
 // memory.  Rounds alternate between parity 0 and 1 so that one round's
@@ -1278,7 +1279,9 @@ __global__ __launch_bounds__(kBlock) void k_bag_extract(LanePair P) {
         if (threadIdx.x < kWave) policy_forward_wave(S.policy_w, x, y, h1, h2);
         __syncthreads();
         if (threadIdx.x == 0)
-            policy_pick(y, 1u, S.fallback_tau, &rc->tau_cur, &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks);
+            // single-source lanes may also pick the dense (pull) mode of Section 4.2
+            policy_pick(y, S.kind == kKindExpandSingle ? 3u : 1u, S.fallback_tau, &rc->tau_cur, &rc->mode_pref,
+                        &rc->policy_calls, &rc->policy_fallbacks);
     }
 }
 
@@ -1641,7 +1644,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_union(int32_t n, int64_t m, const
         }
     }
     unsigned long long c[kNumCtr] = {0, 0, c_arcs, c_unions, 0, 0};
-    block_flush_ctr(cn->c[blockIdx.x % kCtrStripes][kKindPull], c);
+    block_flush_ctr(cn->c[blockIdx.x % kCtrStripes][kKindUnion], c);
 }
 
 // Final component of every vertex as a finished SCC-style key (~root), so

@@ -134,11 +134,12 @@ struct PolicyLane {
     const uint32_t *lsdepth;           // deepest local search of the previous round
     float nsub;                        // subproblem size
     uint32_t *tau_cur, *mode_pref, *calls, *fallbacks;
+    uint32_t mode_mask;                // bit m allows frontier mode m (dense only for single-source lanes)
 };
 
 // The policy step before a round, one launch for up to two lanes (block b =
 // lane b, one wave each).
-__global__ __launch_bounds__(64) void k_policy_round(const float *W, PolicyLane L0, PolicyLane L1, uint32_t mode_mask,
+__global__ __launch_bounds__(64) void k_policy_round(const float *W, PolicyLane L0, PolicyLane L1,
                                                      uint32_t fallback_tau) {
     __shared__ float x[kPolicyIn], h1[kPolicyHidden], h2[kPolicyHidden], y[kPolicyOut];
     const PolicyLane &L = blockIdx.x == 0 ? L0 : L1;
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(64) void k_policy_round(const float *W, PolicyLane 
     __syncthreads();
     policy_forward_wave(W, x, y, h1, h2);
     __syncthreads();
-    if (threadIdx.x == 0) policy_pick(y, mode_mask, fallback_tau, L.tau_cur, L.mode_pref, L.calls, L.fallbacks);
+    if (threadIdx.x == 0) policy_pick(y, L.mode_mask, fallback_tau, L.tau_cur, L.mode_pref, L.calls, L.fallbacks);
 }
 
 inline void policy_release(Policy &p) {

@@ -131,6 +131,10 @@ struct scc_ctx {
     // whether the current call must not allocate (buffers are carved views)
     uint8_t *scratch = nullptr;
     bool noalloc = false;
+    // options.graph_rounds: captured blocks of sparse rounds, keyed by the
+    // block's round count and its lanes' launch arguments
+    bool graph_rounds = false;
+    std::vector<std::pair<std::vector<uint8_t>, hipGraphExec_t>> gcache;
     // statistics of the last scc_bag_selftest: (round, chunk, load, cause) for
     // every chunk left before its round's ExtractAll, and each round's used
     // prefix
@@ -466,9 +470,9 @@ struct DriveParams {
 unsigned extract_blocks(scc_ctx *c) { return (unsigned)std::max(c->num_cu / 2, 1); }
 
 // Before a round: the learned policy picks each sparse lane's budget on the
-// device (one launch for the round's lanes); exploration draws a random
-// budget class per lane.  The frontier mode stays with the direction rule
-// (dense rounds were too rare in the training traces to rank them).
+// device (one launch for the round's lanes), and for a single-source lane
+// also the frontier mode of the next round, which the host applies at its
+// checks; exploration draws a random budget class per lane.
 void launch_policy(scc_ctx *c, Lane **ls, int nl, const scc_options_t &o) {
     if (nl == 0) return;
     if (o.policy == 1 && c->policy.loaded) {
@@ -487,12 +491,13 @@ void launch_policy(scc_ctx *c, Lane **ls, int nl, const scc_options_t &o) {
             if (L.policy_primed && !c->tracing) continue;
             RoundCtl *rc = L.S.rc;
             P[np++] = PolicyLane{rc->nF, &rc->fdeg[L.par], &rc->claims, &rc->rounds, &rc->lsdepth[L.par ^ 1],
-                                 (float)L.nsub, &rc->tau_cur, &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks};
+                                 (float)L.nsub, &rc->tau_cur, &rc->mode_pref, &rc->policy_calls, &rc->policy_fallbacks,
+                                 L.mode == kSingle ? 3u : 1u};
             L.policy_primed = true;
         }
         if (np) {
             hipLaunchKernelGGL(k_policy_round, dim3(np), dim3(64), 0, c->stream, c->policy.w, P[0], P[np > 1 ? 1 : 0],
-                               1u, (uint32_t)std::max(o.tau, 0));
+                               (uint32_t)std::max(o.tau, 0));
             LAUNCHCHK("k_policy_round");
         }
     } else if (o.policy == 2) {
@@ -624,6 +629,51 @@ void launch_dense(scc_ctx *c, Lane &L) {
     L.par ^= 1;
 }
 
+// options.graph_rounds: k sparse rounds of the lanes sp as one HIP graph.
+// The block is captured the first time (the launches are exactly those of
+// launch_sparse) and replayed whenever a block with the same round count,
+// lanes and launch arguments comes again (the bag's per-round salt, which
+// only decorrelates stripe choices, repeats with the graph).
+void run_graph_block(scc_ctx *c, Lane **sp, int nsp, int k) {
+    std::vector<uint8_t> key(2 * sizeof(int) + (size_t)nsp * (sizeof(Search) + sizeof(int)));
+    uint8_t *q = key.data();
+    memcpy(q, &k, sizeof(int));
+    memcpy(q + sizeof(int), &nsp, sizeof(int));
+    q += 2 * sizeof(int);
+    for (int j = 0; j < nsp; j++) {
+        Search s = sp[j]->S;
+        s.bag.salt = 0;
+        s.par = sp[j]->par;
+        memcpy(q, &s, sizeof(Search));
+        memcpy(q + sizeof(Search), &sp[j]->mode, sizeof(int));
+        q += sizeof(Search) + sizeof(int);
+    }
+    for (auto &e : c->gcache)
+        if (e.first == key) {
+            HIPCHK(hipGraphLaunch(e.second, c->stream));
+            for (int j = 0; j < nsp; j++) sp[j]->par ^= (k & 1);
+            return;
+        }
+    if (c->gcache.size() >= 64) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (auto &e : c->gcache) (void)hipGraphExecDestroy(e.second);
+        c->gcache.clear();
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    for (int r = 0; r < k; r++) launch_sparse(c, sp, nsp);
+    HIPCHK(hipStreamEndCapture(c->stream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        set_err(c, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        throw Fail{SCC_EHIP};
+    }
+    c->gcache.push_back({std::move(key), ex});
+    HIPCHK(hipGraphLaunch(ex, c->stream));
+}
+
 // A multi-source lane whose reach table or frontier buffers overflowed
 // restarts on a table twice as large, with buffers to match (Section 4.5
 // resizes once an insertion probes too often; the table cannot grow while
@@ -726,7 +776,24 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
         }
         if (!any) break;
         const int k = (watch || c->tracing) ? 1 : K;
-        for (int r = 0; r < k; r++) {
+        bool graphed = false;
+        if (c->graph_rounds && !c->tracing && !c->timing && !use_policy && k >= 2) {
+            // a block of plain sparse rounds (no pull round, no host-side
+            // policy step) runs as one captured graph
+            Lane *gl[2];
+            int ng = 0;
+            bool ok = true;
+            for (int i = 0; i < nl; i++) {
+                if (!lanes[i].live) continue;
+                if (lanes[i].dense) ok = false;
+                gl[ng++] = &lanes[i];
+            }
+            if (ok && ng > 0 && !(ng == 2 && gl[0]->mode != gl[1]->mode)) {
+                run_graph_block(c, gl, ng, k);
+                graphed = true;
+            }
+        }
+        for (int r = 0; r < (graphed ? 0 : k); r++) {
             // sparse lanes of this round share their launches (traced rounds
             // are timed per lane, so they launch alone)
             Lane *sp[2];
@@ -747,6 +814,13 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
                 if (L.dense) {
                     launch_dense(c, L);
                     c->dense_rounds++;
+                    if (use_policy && !c->tracing) {
+                        // a pull round has no ExtractAll: the policy runs in a
+                        // launch of its own for the next round's mode
+                        L.policy_primed = false;
+                        Lane *one = &L;
+                        launch_policy(c, &one, 1, o);
+                    }
                 } else if (c->tracing) {
                     Lane *one = &L;
                     launch_sparse(c, &one, 1);
@@ -823,6 +897,13 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
                 const bool want_dense = (int64_t)L.nf * 256 > L.nsub && (c->explore_state >> 63);
                 to_dense = !L.dense && want_dense;
                 to_sparse = L.dense && !want_dense;
+            } else if (use_policy && dense_opt == -1 && !c->tracing) {
+                // the policy's mode for the next round (Section 4.2 dense
+                // mode): 1 lets the direction rule switch to pull rounds,
+                // 0 keeps (or brings) the search sparse
+                const bool allow = rc.mode_pref == 1;
+                to_dense = !L.dense && allow && L.fdeg > arcs_on;
+                to_sparse = L.dense && (!allow || (int64_t)L.nf < back_off);
             } else {
                 to_dense = !L.dense && (dense_opt == 1 || L.fdeg > arcs_on);
                 to_sparse = L.dense && dense_opt == -1 && (int64_t)L.nf < back_off;
@@ -925,6 +1006,7 @@ void init_call(scc_ctx *c, scc_stats_t *st, int64_t n, int64_t m, const scc_opti
     HIPCHK(hipSetDevice(c->device));
     c->err.clear();
     c->timing = o ? (uint32_t)o->timing : 0u;
+    c->graph_rounds = o && o->graph_rounds == 1 && !c->noalloc;
     c->arcs_per_lane = (o && o->arcs_per_lane > 0) ? o->arcs_per_lane : 1;
     c->vgc_fill = (o && o->vgc_fill != 0.f) ? (double)o->vgc_fill : 2.0;
     if (c->timing && !c->tev[0][0])
@@ -1024,6 +1106,9 @@ void fill_counters(scc_ctx *c, scc_stats_t *st, int64_t n) {
     st->bytes_kernel[SCC_KERNEL_EXTRACT] =
         (int64_t)(ctr_kind(cn, kKindExpandSingle, kCtrInserts) + ctr_kind(cn, kKindExpandMulti, kCtrInserts) +
                   ctr_kind(cn, kKindHeavySingle, kCtrInserts) + ctr_kind(cn, kKindHeavyMulti, kCtrInserts)) * 24;
+    st->bytes_kernel[SCC_KERNEL_UNION] = (int64_t)(ctr_kind(cn, kKindUnion, kCtrArcs) * 8 +
+                                                   ctr_kind(cn, kKindUnion, kCtrAttempts) * 16) +
+                                         (ctr_kind(cn, kKindUnion, kCtrArcs) ? 12 * n : 0);
     st->bytes_kernel[2] = (int64_t)(ctr_kind(cn, kKindPull, kCtrExpanded) * 8 + ctr_kind(cn, kKindPull, kCtrArcs) * 8) +
                           c->dense_rounds * (n / 4);
     // whole call: searches (expand, edge-parallel, pull), bag traffic
@@ -1441,7 +1526,7 @@ void accumulate_stats(scc_stats_t &acc, const scc_stats_t &st) {
     acc.policy_calls += st.policy_calls;
     acc.policy_fallbacks += st.policy_fallbacks;
     acc.bytes_alg += st.bytes_alg;
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < SCC_KERNELS; k++) {
         acc.ms_kernel[k] += st.ms_kernel[k];
         acc.launches_kernel[k] += st.launches_kernel[k];
         acc.bytes_kernel[k] += st.bytes_kernel[k];
@@ -1668,6 +1753,8 @@ void scc_destroy(scc_ctx_t *c) {
     for (int i = 0; i < 2; i++) { release(c->lk[i]); release(c->gk[i]); release(c->ld[i]); release(c->gd[i]); }
     release(c->lkeep);
     policy_release(c->policy);
+    for (auto &e : c->gcache) (void)hipGraphExecDestroy(e.second);
+    c->gcache.clear();
     if (c->dctl) (void)hipFree(c->dctl);
     if (c->hctl) (void)hipHostFree(c->hctl);
     for (auto &a : c->tev)
@@ -2076,9 +2163,11 @@ scc_status scc_cc(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, const
             ensure(c, c->bstart, (uint64_t)nb + 1);
             hipLaunchKernelGGL(k_arc_block_starts, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n,
                                g->out_off, (int64_t)kUnionArcs, c->bstart.p);
+            const int tu = timed_begin(c, SCC_KERNEL_UNION);
             hipLaunchKernelGGL(k_cc_union, dim3((unsigned)std::min<int64_t>(nb, (int64_t)c->num_cu * 16)), dim3(kBlock),
                                0, c->stream, n, m, g->out_off, g->out_adj, owner, parent, c->bstart.p, &c->dctl->cn);
             LAUNCHCHK("k_cc_union");
+            timed_end(c, tu);
         }
         hipLaunchKernelGGL(k_cc_finish, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, owner, parent,
                            c->label.p);
@@ -2090,6 +2179,7 @@ scc_status scc_cc(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, const
         LAUNCHCHK("k_cc_finish / canonical");
         phase_end(c, ph);
         sync_ctl(c, stats != nullptr);
+        timed_collect(c);
         if (c->hctl->sh.bad & kErrUnfinished) { set_err(c, "internal: a vertex ended without a component"); throw Fail{SCC_EINTERNAL}; }
         if (stats) {
             double ms[kPhases] = {0, 0, 0, 0, 0};

@@ -9,16 +9,17 @@ task) with frontier mode m (0 sparse, 1 dense).  The library takes the best allo
 
 Training data come from graphs whose seeds (>= 10^6) are disjoint from the
 benchmark inputs.  For every training graph each budget class is run with a
-fixed budget, timed end to end, and traced (one feature row per round).
-Every traced row of a graph is labelled, for each class c, with the score
--log(T(c) / min_c' T(c')), where T(c) is the graph's whole-run time with
-class c: the regret of that class on graphs whose rounds look like this one.
-The classes other than the default budget's lose a 3% margin, so the
-policy departs from the fixed schedule only where the traces show a clear
-win.  The MLP regresses the four sparse-mode scores (the dense outputs are
-not trained: the frontier mode stays with the direction rule), so at run
-time it picks, round by round, the class that did best on rounds of that
-kind.
+fixed budget, once with pull rounds allowed (Section 4.2's direction rule)
+and once sparse only, timed end to end, and traced (one feature row per
+round).  Every traced row of a graph is labelled, for each class c and
+mode m, with the score -log(T(c, m) / min T), where T(c, m) is the graph's
+whole-run time with that setting: the regret of that action on graphs whose
+rounds look like this one.  Settings other than the default (class 2, pull
+allowed) lose a 3% margin, so the policy departs from the fixed schedule
+only where the traces show a clear win.  Rows of single-source rounds train
+all eight outputs; rows of multi-source rounds (which have no dense mode)
+the four sparse ones.  At run time mode 1 lets the direction rule switch a
+single-source search to pull rounds and mode 0 keeps it sparse.
 An earlier target, the round's own progress rate, was dominated by state
 noise and picked budgets that lost on every benchmark graph.  The policy
 only chooses schedules: the SCC labels do not depend on it.
@@ -69,8 +70,18 @@ def dataset(rows, scores):
     x = rows[:, 1:6].astype(np.float32)
     y = np.zeros((len(rows), N_OUT), np.float32)
     mask = np.zeros((len(rows), N_OUT), np.float32)
-    y[:, 0::2] = scores
-    mask[:, 0::2] = 1.0
+    scores = np.asarray(scores, np.float32)
+    if scores.shape[1] == N_OUT // 2:
+        # budget classes only: the sparse-mode outputs
+        y[:, 0::2] = scores
+        mask[:, 0::2] = 1.0
+    else:
+        # class x mode scores (output 2c + m); multi-source rows (kind 2)
+        # have no dense mode, so they train the sparse outputs only
+        y[:] = scores
+        single = rows[:, 0] < 2
+        mask[:, 0::2] = 1.0
+        mask[single, 1::2] = 1.0
     return x, mask, y
 
 def fit(rows, scores, steps=4000, lr=3e-3, seed=0, verbose=True):
@@ -130,8 +141,9 @@ def training_graphs():
 
 
 def collect(repeats=4, verbose=True):
-    """For every training graph and budget class: the whole-run time with that
-    fixed budget (best of `repeats`) and one traced run's rows."""
+    """For every training graph, budget class and mode setting (pull rounds
+    allowed, sparse only): the whole-run time (best of `repeats`), and one
+    traced run's rows per class (pull allowed)."""
     import time
 
     import torch
@@ -144,16 +156,17 @@ def collect(repeats=4, verbose=True):
         t_g = []
         for c in range(4):
             tau = 512 << c
-            o = scc.default_options(tau=tau, validate=0, seed=1_000_003 + gi)
-            scc.scc_labels(dg, o, out=out)
-            ts = []
-            for _ in range(repeats):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
+            for dense in (0, -1):  # output 2c + m: m = 0 sparse only, m = 1 pull allowed
+                o = scc.default_options(tau=tau, validate=0, seed=1_000_003 + gi, dense=dense)
                 scc.scc_labels(dg, o, out=out)
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t0)
-            t_g.append(min(ts))
+                ts = []
+                for _ in range(repeats):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    scc.scc_labels(dg, o, out=out)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                t_g.append(min(ts))
             o.trace = 1
             scc.scc_labels(dg, o, out=out)
             t = scc.trace_read()
@@ -166,6 +179,7 @@ def collect(repeats=4, verbose=True):
 
 
 DEFAULT_CLASS = 2   # the library's default budget (2048) is class 2
+DEFAULT_OUTPUT = 2 * DEFAULT_CLASS + 1  # ... with pull rounds allowed
 MARGIN = 0.03       # another class must win by 3% to be preferred
 
 
@@ -176,7 +190,7 @@ def scores_for(gids, times, margin=MARGIN):
     t = np.asarray(times, np.float64)
     sc = -np.log(t / t.min(axis=1, keepdims=True))
     other = np.ones(sc.shape[1], bool)
-    other[DEFAULT_CLASS] = False
+    other[DEFAULT_CLASS if sc.shape[1] == N_OUT // 2 else DEFAULT_OUTPUT] = False
     sc[:, other] -= margin
     return sc[np.asarray(gids)].astype(np.float32)
 

@@ -44,3 +44,14 @@ def test_source_hash_covers_the_kernel_sources():
     bench = load_bench()
     h = bench.source_hash()
     assert len(h) == 16 and h == bench.source_hash()
+
+
+def test_kernel_names_follow_the_search_mode():
+    bench = load_bench()
+    assert bench.kernel_name(1, "scc", 1) == "hipscc::k_expand<2, 1>"
+    assert bench.kernel_name(1, "scc", 0) == "hipscc::k_expand<1, 1>"
+    assert bench.kernel_name(4, "scc", 1) == "hipscc::k_expand_heavy<2>"
+    assert bench.kernel_name(0, "cc") == "hipscc::k_expand<3, 1>"
+    assert bench.kernel_name(6, "cc") == "hipscc::k_cc_union"
+    assert bench.kernel_name(1, "le") == "hipscc::k_expand<4, 1>"
+    assert len(bench.KERNEL_SHORT) == bench.NK == 7

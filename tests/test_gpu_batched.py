@@ -65,3 +65,20 @@ def test_batch_split_into_several_unions(gpu):
     for g, gr in enumerate(graphs):
         assert np.array_equal(got[vb[g]:vb[g + 1]], oracle.scc_graph(gr)), "graph %d" % g
     assert st["n_scc"] == sum(len(np.unique(oracle.scc_graph(gr))) for gr in graphs)
+
+
+def test_batch_with_graph_rounds_and_learned_policy(gpu):
+    import os
+    import torch
+    graphs = graphgen.batched(120, seed=4545, lo_exp=2.0, hi_exp=3.8)
+    vb, ab, oo, oa, io, ia = graphgen.concat(graphs)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+    arrs = (t(oo), t(oa), t(io), t(ia))
+    gpu.policy_load(np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                         "paper_2303_04934_amd", "policy_weights.npy")))
+    for opts in (gpu.default_options(graph_rounds=1), gpu.default_options(policy=1)):
+        for rep in range(2):
+            print("[case] batch graph_rounds=%d policy=%d rep %d" % (opts.graph_rounds, opts.policy, rep), flush=True)
+            got = gpu.scc_labels_batched(vb, ab, *arrs, options=opts).cpu().numpy()
+            for g, gr in enumerate(graphs):
+                assert np.array_equal(got[vb[g]:vb[g + 1]], oracle.scc_graph(gr)), "graph %d" % g

@@ -88,13 +88,29 @@ def test_first_slot_families(gpu, first):
         assert st["table_restarts"] > 0
 
 
+def test_graph_rounds_replays_match_the_oracle(gpu):
+    # blocks of sparse rounds as captured HIP graphs: every call replays the
+    # cached graphs, with the library's own eager launches and host checks
+    # between replays; each call's labels must stay exact
+    opts = gpu.default_options(graph_rounds=1)
+    for g in (graphgen.grid(300, 300, 0.5, seed=65), graphgen.knn(60000, 6, 5, 0.01, seed=66),
+              graphgen.rmat(14, 8, seed=67)):
+        for rep in range(3):
+            check_labels(gpu, g, opts, name="%s graph_rounds rep %d" % (g.name, rep))
+    check_labels(gpu, graphgen.from_arcs(20000, np.arange(19999), np.arange(1, 20000)),
+                 gpu.default_options(graph_rounds=1, table_init=1024, table_floor=0.0, first_slot=0),
+                 name="path20000 graph_rounds restarts")
+
+
 def test_forced_small_table_restarts(gpu):
     # a path: the first search splits it into two long subproblems, so the
     # next batch's sources reach thousands of vertices in some direction,
     # far more than a 1024-slot table holds
     n = 20000
     g = graphgen.from_arcs(n, np.arange(n - 1), np.arange(1, n))
-    st = check_labels(gpu, g, gpu.default_options(table_init=1024, table_floor=0.0), name="path20000 small table")
+    # (pairs in the table only: first-source slots would take the first pair of every vertex)
+    st = check_labels(gpu, g, gpu.default_options(table_init=1024, table_floor=0.0, first_slot=0),
+                      name="path20000 small table")
     assert st["table_restarts"] > 0
 
 

@@ -93,3 +93,20 @@ def test_autotune_sample_is_a_strict_subset_and_held_out_is_the_rest():
             assert len(set(idx) & set(rest)) == 0
             # every second graph: the sample keeps about half the batch
             assert abs(len(idx) - G / 2) <= 1
+
+
+def test_class_and_mode_labels_train_dense_outputs_on_single_source_rows_only():
+    import numpy as np
+
+    from paper_2303_04934_amd import policy_train as pt
+    rows = np.zeros((3, 12), np.float32)
+    rows[:, 0] = [0, 1, 2]  # sparse single-source, dense single-source, multi-source
+    times = np.array([[4.0, 3.0, 2.5, 2.0, 2.2, 1.0, 3.0, 3.5]])  # T(c, m), output 2c + m
+    sc = pt.scores_for(np.zeros(3, np.int32), times, margin=0.0)
+    x, mask, y = pt.dataset(rows, sc)
+    assert mask[0].tolist() == [1] * 8 and mask[1].tolist() == [1] * 8
+    assert mask[2].tolist() == [1, 0, 1, 0, 1, 0, 1, 0]
+    assert np.argmax(y[0]) == 5  # the fastest setting scores 0, the others below
+    # the margin lowers every setting but the default (class 2, pull allowed)
+    sc2 = pt.scores_for(np.zeros(1, np.int32), times, margin=0.03)
+    assert sc2[0, pt.DEFAULT_OUTPUT] == sc[0, pt.DEFAULT_OUTPUT] and sc2[0, 0] < sc[0, 0]
