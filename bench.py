@@ -180,6 +180,44 @@ def roofline(ms_k, launches_k, bytes_k, dom, workload, name):
             "avg_launch_ms": per_launch_ms, "alg_bytes_per_launch": per_launch_bytes}
 
 
+def parse_variants(text):
+    """'k=v,k=v;k=v' -> list of option-override dicts (A/B runs in one process)."""
+    out = []
+    for part in filter(None, (p.strip() for p in text.split(";"))):
+        d = {}
+        for kv in part.split(","):
+            k, v = kv.split("=")
+            d[k.strip()] = float(v) if "." in v else int(v)
+        out.append(d)
+    return out
+
+
+def time_variants(call, base, variants, steps):
+    """Whole-call times of option variants (no kernel events): a warm-up
+    call, then `steps` timed calls each."""
+    import torch
+
+    import paper_2303_04934_amd as scc
+    res = []
+    for v in variants:
+        o = scc.default_options()
+        for f, _ in o._fields_:
+            setattr(o, f, getattr(base, f))
+        o.timing = 0
+        for k, x in v.items():
+            setattr(o, k, x)
+        call(o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call(o)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        log("variant %s: %.3f ms per call" % (v, ms))
+        res.append({"options": v, "ms_per_call": ms})
+    return res
+
+
 def load_policy(scc):
     import numpy as np
     scc.policy_load(np.load(os.path.join(ROOT, "paper_2303_04934_amd", "policy_weights.npy")))
@@ -241,8 +279,12 @@ def run_batched(args, desc):
     got = out.cpu().numpy()
     log("timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3))
     if args.profile_only:
-        print(json.dumps({"workload": "batched4096", "ms_per_step": dt * 1e3, "steps": args.steps,
-                          "schedule": [opts.tau, opts.beta, opts.beta_fast, opts.policy]}), flush=True)
+        rec = {"workload": "batched4096", "ms_per_step": dt * 1e3, "steps": args.steps,
+               "schedule": [opts.tau, opts.beta, opts.beta_fast, opts.policy]}
+        if args.variants:
+            rec["variants"] = time_variants(lambda o: scc.scc_labels_batched(vb, ab, *arrs, options=o), opts,
+                                            parse_variants(args.variants), args.steps)
+        print(json.dumps(rec), flush=True)
         return
 
     # comparisons (untimed region), with the same event overhead as the timed steps
@@ -376,8 +418,12 @@ def run_single(args, cfg, desc):
     last = stats[-1]
     line["stats"] = {k: last[k] for k in ("ms_trim", "ms_first", "ms_multi", "ms_resize", "ms_label", "batches",
                                          "rounds_first", "rounds_multi", "dense_rounds", "trimmed", "n_scc",
-                                         "arcs_scanned", "claims", "bag_inserts", "table_restarts", "bytes_alg")}
+                                         "arcs_scanned", "claims", "claims_table", "bag_inserts", "table_restarts",
+                                         "bytes_alg")}
     line["stats"]["alg_GBps_whole_step"] = last["bytes_alg"] / dt / 1e9
+    if args.variants:
+        line["variants"] = time_variants(lambda o: scc.scc_labels(dg, o, out=out), opts, parse_variants(args.variants),
+                                         args.steps)
     # every frontier kernel's event time in the (untimed) warm-up call that picked the dominant one
     line["stats"]["kernel_ms_warmup_call"] = {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)}
     if not args.no_cpu_baseline:
@@ -448,6 +494,8 @@ def run_app(args, cfg, desc):
                                          "rounds_multi", "n_scc", "arcs_scanned", "claims", "bag_inserts",
                                          "table_restarts", "bytes_alg")}
     line["stats"]["kernel_ms_warmup_call"] = {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)}
+    if args.variants:
+        line["variants"] = time_variants(lambda o: call(o), opts, parse_variants(args.variants), args.steps)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         if args.app == "cc":
@@ -484,6 +532,7 @@ def main():
     ap.add_argument("--first-slot", type=int, default=-1, help="options.first_slot (-1: the library default)")
     ap.add_argument("--vgc-measure", type=int, default=0, help="options.vgc_measure (0 arcs, 1 claims)")
     ap.add_argument("--graph-rounds", type=int, default=0, help="options.graph_rounds (captured round blocks)")
+    ap.add_argument("--variants", default="", help="also time option variants: 'k=v,k=v;k=v' (A/B, one process)")
     ap.add_argument("--batch-hi", type=float, default=6.0,
                     help="batched workload: vertex counts log-uniform in [1e3, 10**batch_hi]")
     ap.add_argument("--schedule", default="", help="batched: tau,beta,beta_fast,policy instead of autotuning")

@@ -142,6 +142,12 @@ typedef struct {
  *                vertices for a single source).
  *   ldd_beta     scc_cc: growth of the centre batches of the low-diameter
  *                decomposition per round (Section 5.1 uses 1.2; default).
+ *   packed       with first_slot: 1 = the multi-source searches read packed
+ *                per-vertex records {first arc, degree, label, first-source
+ *                slot} of 16 bytes (one memory sector per claim instead of
+ *                three), built once per call; 0 = separate arrays; -1
+ *                (default) = records when more than half the vertices
+ *                survive trimming (the build pass is then worth it).
  *   graph_rounds 1 = a block of sparse rounds between two host checks runs
  *                as one captured HIP graph, replayed when a block with the
  *                same round count and launch arguments comes again (cached
@@ -173,6 +179,7 @@ typedef struct {
     int32_t vgc_measure;
     float ldd_beta;
     int32_t graph_rounds;
+    int32_t packed;
 } scc_options_t;
 
 /* Frontier kernels timed with options.timing. */
@@ -201,6 +208,7 @@ typedef struct {
     int64_t arcs_scanned;     /* adjacency slots read by searches */
     int64_t claim_attempts;   /* label-equal targets that were tried */
     int64_t claims;           /* successful claims = reachability pairs found */
+    int64_t claims_table;     /* of those (first-source slots on), the pairs that went to the reach table */
     int64_t bag_inserts;      /* hash bag inserts */
     int64_t bag_chunk_advances;
     int64_t table_restarts;   /* searches re-run with a larger table */

@@ -35,14 +35,14 @@ class Options(ctypes.Structure):
                 ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float),
                 ("beta_fast", ctypes.c_float), ("table_floor", ctypes.c_float), ("union_arcs_max", ctypes.c_int32),
                 ("first_slot", ctypes.c_int32), ("vgc_measure", ctypes.c_int32), ("ldd_beta", ctypes.c_float),
-                ("graph_rounds", ctypes.c_int32)]
+                ("graph_rounds", ctypes.c_int32), ("packed", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_double) for f in ("ms_total", "ms_trim", "ms_first", "ms_multi", "ms_resize",
                                                 "ms_label")] + \
                [(f, ctypes.c_int64) for f in ("n", "m", "batches", "rounds_first", "rounds_multi", "dense_rounds",
-                                               "entries_expanded", "arcs_scanned", "claim_attempts", "claims",
+                                               "entries_expanded", "arcs_scanned", "claim_attempts", "claims", "claims_table",
                                                "bag_inserts", "bag_chunk_advances", "table_restarts", "restart_rounds", "trimmed",
                                                "n_scc", "policy_calls", "policy_fallbacks", "bytes_alg")] + \
                [("ms_kernel", ctypes.c_double * KERNELS), ("launches_kernel", ctypes.c_int64 * KERNELS),

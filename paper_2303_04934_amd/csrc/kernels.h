@@ -34,6 +34,7 @@ struct RoundCtl {
     uint32_t snap_rounds, snap_depth;  // trace snapshot of the round's inputs
     unsigned long long snap_nf, snap_fdeg, snap_claims;
     uint32_t pad2;
+    unsigned long long tclaims;  // of the claims, those that went to the reach table (first-source slots on)
 };
 
 // Striped round counters of one lane.  Atomics on one address from many
@@ -46,7 +47,8 @@ struct alignas(128) StripeLine {
     uint32_t depth;             // this round's deepest local search
     uint32_t nf;                // this round's next-frontier size (dense rounds)
     uint32_t work[2];           // dynamic group counters of the expand kernel, per parity
-    uint32_t pad[26];
+    unsigned long long tclaims; // cumulative claims that went to the reach table
+    uint32_t pad[24];
 };
 static_assert(sizeof(StripeLine) == 128, "one cache line per stripe");
 struct LaneStripes {
@@ -62,16 +64,18 @@ __device__ __forceinline__ void stripes_clear(LaneStripes *ls) {
 // Round-end fold (one thread): claims and the round's local-search depth
 // into RoundCtl; this parity's work counters and the depth lines restart.
 __device__ __forceinline__ void stripes_fold(RoundCtl *rc, LaneStripes *ls, int par) {
-    unsigned long long c = 0;
+    unsigned long long c = 0, tc = 0;
     uint32_t d = 0;
     for (int i = 0; i < kStripes; i++) {
         StripeLine &L = ls->s[i];
         c += L.claims;
+        tc += L.tclaims;
         d = L.depth > d ? L.depth : d;
         L.depth = 0;
         L.work[par] = 0;
     }
     rc->claims = c;
+    rc->tclaims = tc;
     rc->lsdepth[par] = d;
 }
 
@@ -111,13 +115,16 @@ constexpr int kQmask = kQcap - 1;
 constexpr int kStepArcs = 256;  // arcs a wave commits to per local-search step
 constexpr int kHeavyChunk = 4096;  // arcs per edge-parallel work item
 
-enum { kSingle = 0, kMulti = 1, kMultiFirst = 2, kLdd = 3, kLe = 4 };
+enum { kSingle = 0, kMulti = 1, kMultiFirst = 2, kLdd = 3, kLe = 4, kMultiRec = 5 };
 
 // One reachability search (one direction).  kSingle claims vertices in a
 // visited bitmap whose bits were pre-set for every vertex outside the search's
 // subproblem; kMulti claims (vertex, source) pairs in the reach table;
 // kMultiFirst claims the first pair of each vertex in a per-vertex slot
 // (first[v] = source index) and only later pairs in the reach table.  kLdd
+// kMultiRec is kMultiFirst on packed per-vertex records {first arc, degree,
+// label, first-source slot} (16 bytes, one memory sector per claim instead
+// of the label, slot and offsets arrays).  kLdd
 // is kSingle for the low-diameter decomposition of Algorithm 4: an entry
 // carries its cluster centre in place of the source index, and a claim also
 // records owner[w] = centre.  kLe is the pruned multi-BFS of Algorithm 5 (LE
@@ -131,6 +138,7 @@ struct Search {
     uint32_t *vis;          // kSingle
     uint64_t *table;        // kMulti
     int32_t *first;         // kMultiFirst: per-vertex first-source slot (-1 = empty)
+    int4 *rec;              // kMultiRec: per-vertex {first arc, degree, label, first-source slot}
     int32_t *owner;         // kLdd: cluster centre of each claimed vertex
     int32_t level;          // kLe: distance of the entries this round expands
     uint64_t tmask;
@@ -423,18 +431,27 @@ __device__ __forceinline__ int claim_pair(uint64_t *T, uint64_t mask, uint32_t l
 
 // A pair claim with the inline first-source slot: the slot of w holds the
 // first source that reached w; a pair of any other source goes to the table.
-// Returns like claim_pair.
-__device__ __forceinline__ int claim_pair_first(int32_t *first, uint64_t *T, uint64_t mask, uint32_t limit, int32_t w,
-                                                uint32_t src) {
-    const int32_t f = (int32_t)ld_relaxed(reinterpret_cast<const uint32_t *>(first + w));
+// Returns like claim_pair, except that a new pair claimed in the table
+// returns 2.
+__device__ __forceinline__ int claim_pair_slot(int32_t *slot, uint64_t *T, uint64_t mask, uint32_t limit, int32_t w,
+                                               uint32_t src) {
+    const int32_t f = (int32_t)ld_relaxed(reinterpret_cast<const uint32_t *>(slot));
     if (f == (int32_t)src) return 0;
     if (f == -1) {
-        const int32_t old = atomicCAS(first + w, -1, (int32_t)src);
+        const int32_t old = atomicCAS(slot, -1, (int32_t)src);
         if (old == -1) return 1;
         if (old == (int32_t)src) return 0;
     }
-    return claim_pair(T, mask, limit, pair_key(w, src));
+    const int c = claim_pair(T, mask, limit, pair_key(w, src));
+    return c == 1 ? 2 : c;
 }
+__device__ __forceinline__ int claim_pair_first(int32_t *first, uint64_t *T, uint64_t mask, uint32_t limit, int32_t w,
+                                                uint32_t src) {
+    return claim_pair_slot(first + w, T, mask, limit, w, src);
+}
+// The first-source slot of vertex v in a slot array of the given stride
+// (1: plain slots; 4: the last field of packed records).
+__device__ __forceinline__ int32_t *slot_of(int32_t *base, int32_t stride, int64_t v) { return base + stride * v; }
 
 __device__ __forceinline__ bool table_contains(const uint64_t *T, uint64_t mask, uint32_t limit, uint64_t key) {
     uint64_t h = mix64(key) & mask;
@@ -496,6 +513,7 @@ __global__ void k_seed_single(int32_t s_fixed, const Shared *sh, Perm P, uint64_
 struct SeedArgs {
     uint64_t *T[2];
     int32_t *first[2];      // non-null: the lane claims first pairs in per-vertex slots
+    int32_t fstride[2];     // their stride in int32 (1 plain slots, 4 packed records)
     uint64_t mask[2];
     uint64_t *F[2];
     RoundCtl *rc[2];
@@ -509,7 +527,8 @@ __global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, SeedArgs 
     const uint32_t k = sh->k;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
         uint64_t key = pair_key(srcvert[j], j);
-        const int c = A.first[l] ? claim_pair_first(A.first[l], A.T[l], A.mask[l], limit, srcvert[j], j)
+        const int c = A.first[l] ? claim_pair_slot(slot_of(A.first[l], A.fstride[l], srcvert[j]), A.T[l], A.mask[l],
+                                                   limit, srcvert[j], j)
                                  : claim_pair(A.T[l], A.mask[l], limit, key);
         if (c < 0) atomicOr(&rc->err, kErrTable);
         A.F[l][j] = key;
@@ -560,8 +579,9 @@ __global__ void k_batch_reset(Shared *sh, RoundCtl *rc0, RoundCtl *rc1) {
 // its first reach-table probe and its offsets together.
 template <int MODE, int ILP>
 __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint32_t nblk) {
-    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst || MODE == kLe;
-    constexpr bool FIRST = MODE == kMultiFirst;
+    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst || MODE == kLe || MODE == kMultiRec;
+    constexpr bool FIRST = MODE == kMultiFirst || MODE == kMultiRec;
+    constexpr bool REC = MODE == kMultiRec;
     __shared__ uint64_t Qk[kWavesPerBlock][kQcap];                 // (vertex, source) keys
     __shared__ int2 Qr[kWavesPerBlock][kQcap];                     // (first arc, degree)
     __shared__ int32_t Ql[kWavesPerBlock][PAIRS ? kQcap : 1];      // entry's label (multi-source)
@@ -599,7 +619,7 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
     const bool vgc = tau > 1 && ((fd > 0 && S.vgc_arcs > 0) ? fd < S.vgc_arcs : nF < S.vgc_cut);
     uint32_t depth = 0;
     uint32_t wseq = 0;
-    unsigned long long c_seeds = 0, c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
+    unsigned long long c_seeds = 0, c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0, c_tclaims = 0;
 
     // Groups: wave w first takes group w; the groups past the wave count are
     // dealt out through per-stripe counters (wave w draws from stripe
@@ -612,12 +632,18 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
         if (lane < cnt) {
             const uint64_t e = S.F[start + lane];
             const int32_t u = key_vertex(e);
-            const int32_t b0 = S.off[u];
             Q[lane] = e;
-            R[lane] = make_int2(b0, S.off[u + 1] - b0);
             // an entry (u, j) was claimed because label[u] equals source j's
             // label, so the entry carries the label its arcs are tested against
-            if (PAIRS) QL[lane] = S.label[u];
+            if (REC) {
+                const int4 r = S.rec[u];
+                R[lane] = make_int2(r.x, r.y);
+                QL[lane] = r.z;
+            } else {
+                const int32_t b0 = S.off[u];
+                R[lane] = make_int2(b0, S.off[u + 1] - b0);
+                if (PAIRS) QL[lane] = S.label[u];
+            }
         }
         c_seeds += (unsigned long long)cnt;
         int head = 0, tail = cnt;
@@ -774,7 +800,14 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                         o0[j] = o1[j] = 0;
                         fs[j] = -1;
                         nlab[j] = -1;
-                        if (va[j]) {
+                        if (va[j] && REC) {
+                            // one 16-byte record: offsets, label and slot together
+                            const int4 r = S.rec[w[j]];
+                            o0[j] = r.x;
+                            o1[j] = r.x + r.y;
+                            nlab[j] = r.z;
+                            fs[j] = r.w;
+                        } else if (va[j]) {
                             nlab[j] = S.label[w[j]];
                             if (FIRST) {
                                 fs[j] = (int32_t)ld_relaxed(reinterpret_cast<const uint32_t *>(S.first + w[j]));
@@ -795,10 +828,12 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                         c_att += st[j] == 2 ? 1 : 0;
                         nr[j] = make_int2(o0[j], o1[j] - o0[j]);
                     }
+                    bool tab[ILP];
+#pragma unroll
+                    for (int j = 0; j < ILP; j++) tab[j] = false;
                     if (FIRST) {
                         // the inline slot first: already this source's, free
                         // (claim it), or another source's (the pair goes to the table)
-                        bool tab[ILP];
 #pragma unroll
                         for (int j = 0; j < ILP; j++) {
                             tab[j] = false;
@@ -807,7 +842,8 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                             if (fs[j] == src) {
                                 st[j] = 0;
                             } else if (fs[j] == -1) {
-                                const int32_t old = atomicCAS(S.first + w[j], -1, src);
+                                int32_t *sl = REC ? reinterpret_cast<int32_t *>(S.rec + w[j]) + 3 : S.first + w[j];
+                                const int32_t old = atomicCAS(sl, -1, src);
                                 if (old == -1) st[j] = 1;
                                 else if (old == src) st[j] = 0;
                                 else tab[j] = true;
@@ -863,7 +899,10 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                             if (st[j] == 2) cur[j] = ld_relaxed64(S.table + h[j]);
                     }
 #pragma unroll
-                    for (int j = 0; j < ILP; j++) claimed[j] = st[j] == 1;
+                    for (int j = 0; j < ILP; j++) {
+                        claimed[j] = st[j] == 1;
+                        c_tclaims += (FIRST && tab[j] && claimed[j]) ? 1 : 0;
+                    }
                 }
                 // new entries: the local queue while it has room, else the bag
                 int tot = 0, rk[ILP];
@@ -912,6 +951,18 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
     const unsigned long long t = block_flush_ctr(S.cn->c[bid % kCtrStripes][S.kind], c);  // has a barrier
     StripeLine &sl = S.ls->s[bid % kStripes];
     if (threadIdx.x == kCtrClaims && t) atomicAdd(&sl.claims, t);
+    if (FIRST) {
+        // table claims: a block-wide sum, one atomic per block
+        __shared__ unsigned long long tpart[kWavesPerBlock];
+        const unsigned long long tw = wave_sum_u64(c_tclaims);
+        if (lane == 0) tpart[wv] = tw;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tt = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) tt += tpart[w];
+            if (tt) atomicAdd(&sl.tclaims, tt);
+        }
+    }
     if (threadIdx.x == kNumCtr) {
         uint32_t d = 0;
         for (int w = 0; w < kWavesPerBlock; w++) d = dmax[w] > d ? dmax[w] : d;
@@ -951,7 +1002,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(LanePair P) {
 // its four waves stride over the slice; claims go to the bag.
 template <int MODE>
 __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint32_t nblk) {
-    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst || MODE == kLe;
+    constexpr bool PAIRS = MODE == kMulti || MODE == kMultiFirst || MODE == kLe || MODE == kMultiRec;
+    constexpr bool REC = MODE == kMultiRec;
     RoundCtl *rc = S.rc;
     uint32_t nh = ld_relaxed(&rc->heavy_n[S.par]);
     if (nh == 0) return;
@@ -960,18 +1012,18 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
     const int wv = threadIdx.x / kWave;
     const uint32_t wave_gid = bid * kWavesPerBlock + wv;
     uint32_t wseq = 0x8000u;
-    unsigned long long c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0;
+    unsigned long long c_exp = 0, c_arcs = 0, c_att = 0, c_claims = 0, c_ins = 0, c_tclaims = 0;
     for (uint32_t h = bid; h < nh; h += nblk) {
         const uint64_t e = S.heavy[2 * (uint64_t)h];
         if (e == kEmpty64) continue;  // block-uniform
         const uint32_t chunk = (uint32_t)S.heavy[2 * (uint64_t)h + 1];
         const int32_t u = key_vertex(e);
         const uint32_t src = key_source(e);
-        const int32_t beg0 = S.off[u];
-        const int64_t d = (int64_t)S.off[u + 1] - beg0;
+        const int32_t beg0 = REC ? S.rec[u].x : S.off[u];
+        const int64_t d = REC ? (int64_t)S.rec[u].y : (int64_t)S.off[u + 1] - beg0;
         const int64_t lo = (int64_t)chunk * kHeavyChunk;
         const int64_t len = (d - lo) < kHeavyChunk ? (d - lo) : kHeavyChunk;
-        const int32_t lab = (MODE == kMulti || MODE == kMultiFirst) ? S.srclab[src] : 0;
+        const int32_t lab = (MODE == kMulti || MODE == kMultiFirst || REC) ? S.srclab[src] : 0;
         if (chunk == 0 && threadIdx.x == 0) c_exp++;
         for (int64_t base = (int64_t)wv * kWave; base < len; base += kBlock) {
             const int64_t a = base + lane;
@@ -984,13 +1036,16 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
                     c_att++;
                     claimed = claim_bit(S.vis, w);
                     if (MODE == kLdd && claimed) S.owner[w] = (int32_t)src;
-                } else if (MODE == kLe ? S.level + 1 < S.label[w] : S.label[w] == lab) {
+                } else if (MODE == kLe ? S.level + 1 < S.label[w] : (REC ? S.rec[w].z : S.label[w]) == lab) {
                     c_att++;
-                    const int c = MODE == kMultiFirst
+                    const int c = REC ? claim_pair_slot(reinterpret_cast<int32_t *>(S.rec + w) + 3, S.table, S.tmask,
+                                                        S.probe_limit, w, src)
+                                  : MODE == kMultiFirst
                                       ? claim_pair_first(S.first, S.table, S.tmask, S.probe_limit, w, src)
                                       : claim_pair(S.table, S.tmask, S.probe_limit, pair_key(w, src));
                     if (c < 0) atomicOr(&rc->err, kErrTable);
-                    claimed = c == 1;
+                    claimed = c >= 1;
+                    c_tclaims += c == 2 ? 1 : 0;
                 }
                 ne = pair_key(w, src);
             }
@@ -1002,6 +1057,17 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
     const unsigned long long t =
         block_flush_ctr(S.cn->c[bid % kCtrStripes][PAIRS ? kKindHeavyMulti : kKindHeavySingle], c);
     if (threadIdx.x == kCtrClaims && t) atomicAdd(&S.ls->s[bid % kStripes].claims, t);
+    if (MODE == kMultiFirst || REC) {
+        __shared__ unsigned long long tpart[kWavesPerBlock];
+        const unsigned long long tw = wave_sum_u64(c_tclaims);
+        if (lane == 0) tpart[wv] = tw;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tt = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) tt += tpart[w];
+            if (tt) atomicAdd(&S.ls->s[bid % kStripes].tclaims, tt);
+        }
+    }
 }
 
 template <int MODE>
@@ -1317,7 +1383,7 @@ __global__ void k_finish_single(int32_t n, int32_t *label, int32_t L, const Shar
 __global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, uint64_t *Tin, uint64_t min_,
                              uint32_t limit, const int32_t *srcvert, unsigned long long *sig_out,
                              unsigned long long *sig_in, int32_t *fin, bool clear_in, const int32_t *firstF,
-                             const int32_t *firstB) {
+                             const int32_t *firstB, int32_t fstride) {
     // with first-source slots a vertex's pairs are its slot plus its table
     // keys, per direction; the slots themselves are summed by the per-vertex
     // relabel, and a shared source is found here for every combination that
@@ -1329,14 +1395,16 @@ __global__ void k_accumulate(const uint64_t *Tout, uint64_t mout, uint64_t *Tin,
             if (key == kEmpty64) continue;
             const int32_t v = key_vertex(key);
             atomicAdd(&sig_out[v], (unsigned long long)sig_term_out(srcvert[key_source(key)]));
-            if (firstB && firstB[v] == (int32_t)key_source(key)) atomicMin(&fin[v], (int32_t)key_source(key));
+            if (firstB && firstB[(int64_t)fstride * v] == (int32_t)key_source(key))
+                atomicMin(&fin[v], (int32_t)key_source(key));
         } else {
             const uint64_t key = Tin[i - n_out];
             if (key == kEmpty64) continue;
             if (clear_in) Tin[i - n_out] = kEmpty64;
             const int32_t v = key_vertex(key);
             atomicAdd(&sig_in[v], (unsigned long long)sig_term_in(srcvert[key_source(key)]));
-            if ((firstF && firstF[v] == (int32_t)key_source(key)) || table_contains(Tout, mout, limit, key))
+            if ((firstF && firstF[(int64_t)fstride * v] == (int32_t)key_source(key)) ||
+                table_contains(Tout, mout, limit, key))
                 atomicMin(&fin[v], (int32_t)key_source(key));
         }
     }
@@ -1379,7 +1447,8 @@ __global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, ui
 // by k_accumulate.
 __global__ void k_relabel_dense(int32_t n, uint64_t *Tout, uint64_t mout, const int32_t *srcvert,
                                 unsigned long long *sig_out, unsigned long long *sig_in, int32_t *fin, int32_t *label,
-                                CountStripes *cs, int32_t *firstF, int32_t *firstB) {
+                                CountStripes *cs, int32_t *firstF, int32_t *firstB, int32_t fstride, int4 *recF,
+                                int4 *recB) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= mout; i += stride) Tout[i] = kEmpty64;
     uint32_t cnt = 0;
@@ -1391,30 +1460,55 @@ __global__ void k_relabel_dense(int32_t n, uint64_t *Tout, uint64_t mout, const 
         if (firstF) {
             // the first-source slots: their pairs join the signatures, a
             // source in both slots finishes the vertex, and the slots empty
-            const int32_t a = firstF[v], b = firstB[v];
+            int32_t *pa = firstF + (int64_t)fstride * v, *pb = firstB + (int64_t)fstride * v;
+            const int32_t a = *pa, b = *pb;
             if (a >= 0) {
                 so += sig_term_out(srcvert[a]);
-                firstF[v] = -1;
+                *pa = -1;
             }
             if (b >= 0) {
                 si += sig_term_in(srcvert[b]);
-                firstB[v] = -1;
+                *pb = -1;
             }
             if (a >= 0 && a == b && a < f) f = a;
         }
+        int32_t nl;
         if (f != kInf32) {
-            label[v] = ~srcvert[f];
+            nl = ~srcvert[f];
             cnt++;
         } else if ((si | so) != 0ull) {
-            label[v] = relabel_hash(l, si, so);
+            nl = relabel_hash(l, si, so);
         } else {
             continue;
+        }
+        label[v] = nl;
+        if (recF) {  // the packed records carry a copy of the label
+            recF[v].z = nl;
+            recB[v].z = nl;
         }
         sig_in[v] = 0;
         sig_out[v] = 0;
         fin[v] = kInf32;
     }
     block_add_u32(&cs->s[blockIdx.x % kStripes].fin, cnt);
+}
+
+// Packed records of both directions for the multi-source batches: {first
+// arc, degree, label, empty first-source slot}.
+__global__ void k_build_rec(int32_t n, const int32_t *out_off, const int32_t *in_off, const int32_t *label, int4 *recF,
+                            int4 *recB) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t l = label[v];
+        const int32_t a = out_off[v], b = in_off[v];
+        recF[v] = make_int4(a, out_off[v + 1] - a, l, -1);
+        recB[v] = make_int4(b, in_off[v + 1] - b, l, -1);
+    }
+}
+
+// Empties the first-source slots of one direction's records.
+__global__ void k_clear_rec_slots(int32_t n, int4 *rec) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        rec[v].w = -1;
 }
 
 // ---------------------------------------------------------- canonical ----

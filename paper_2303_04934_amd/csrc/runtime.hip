@@ -72,7 +72,7 @@ struct scc_ctx {
     int num_cu = 256;
     uint64_t table_slots_max = 1ull << 24;  // cap of the estimated reach-table size (set from device memory)
     int expand_blocks = 2048;
-    int expand_grid[5][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
+    int expand_grid[6][3] = {};     // resident-grid size per (mode, log2 arcs per lane)
     int arcs_per_lane = 1;          // options.arcs_per_lane of the current call
     double vgc_fill = 2.0;          // options.vgc_fill of the current call
     std::string err;
@@ -84,6 +84,7 @@ struct scc_ctx {
     DevBuf<uint32_t> bm[2][2];      // front/next bitmaps per lane (dense mode)
     DevBuf<uint64_t> Tout, Tin;     // reach tables (forward, backward)
     DevBuf<int32_t> firstS[2];      // first-source slots per direction (options.first_slot)
+    DevBuf<int4> rec[2];            // packed per-vertex records per direction (options.packed)
     int64_t first_clean_n = 0;      // the slots are known empty (-1) on [0, first_clean_n)
     DevBuf<uint64_t> F[2], heavy[2];
     DevBuf<uint64_t> bag_slots[2];
@@ -313,6 +314,7 @@ scc_options_t defaults() {
     o.timing = 0;
     o.ldd_beta = 1.2f;
     o.first_slot = 1;
+    o.packed = -1;
     return o;
 }
 
@@ -361,6 +363,7 @@ void check_opts(scc_ctx *c, const scc_options_t &o) {
     if (o.union_arcs_max < 0) { set_err(c, "union_arcs_max must be >= 0"); throw Fail{SCC_EINVAL}; }
     if (o.first_slot < 0 || o.first_slot > 1) { set_err(c, "first_slot must be 0 or 1"); throw Fail{SCC_EINVAL}; }
     if (o.vgc_measure < 0 || o.vgc_measure > 1) { set_err(c, "vgc_measure must be 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (o.packed < -1 || o.packed > 1) { set_err(c, "packed must be -1, 0 or 1"); throw Fail{SCC_EINVAL}; }
     if (!(o.ldd_beta > 1.0f) || !(o.ldd_beta < 1e6f)) { set_err(c, "ldd_beta must be > 1"); throw Fail{SCC_EINVAL}; }
 }
 
@@ -420,7 +423,8 @@ Search make_search(scc_ctx *c, int id, const scc_options_t &o, int mode) {
     S.rc = &c->dctl->lane[id];
     S.ls = &c->dctl->ls[id];
     S.cn = &c->dctl->cn;
-    S.kind = (mode == kMulti || mode == kMultiFirst || mode == kLe) ? kKindExpandMulti : kKindExpandSingle;
+    S.kind = (mode == kMulti || mode == kMultiFirst || mode == kLe || mode == kMultiRec) ? kKindExpandMulti
+                                                                                        : kKindExpandSingle;
     S.tau = o.tau;
     S.seeds = o.seeds_per_wave;
     S.heavy_deg = 1024;
@@ -533,6 +537,11 @@ void timed_collect(scc_ctx *c) {
 
 // The expand kernel of a search mode and arcs-per-lane setting.
 const void *expand_kernel(int mode, int apl) {
+    if (mode == kMultiRec) {
+        if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kMultiRec, 1>);
+        if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kMultiRec, 2>);
+        return reinterpret_cast<const void *>(&k_expand<kMultiRec, 4>);
+    }
     if (mode == kLe) {
         if (apl == 1) return reinterpret_cast<const void *>(&k_expand<kLe, 1>);
         if (apl == 2) return reinterpret_cast<const void *>(&k_expand<kLe, 2>);
@@ -589,9 +598,10 @@ void launch_sparse(scc_ctx *c, Lane **ls, int nl) {
     HIPCHK(hipLaunchKernel(fn, dim3(eb), dim3(kBlock), args, 0, c->stream));
     timed_end(c, t);
     P.split = hb / 2;
-    const bool pairs = mode == kMulti || mode == kMultiFirst || mode == kLe;
+    const bool pairs = mode == kMulti || mode == kMultiFirst || mode == kLe || mode == kMultiRec;
     const int th = timed_begin(c, pairs ? SCC_KERNEL_HEAVY_MULTI : SCC_KERNEL_HEAVY_SINGLE);
-    if (mode == kLe) hipLaunchKernelGGL(k_expand_heavy<kLe>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    if (mode == kMultiRec) hipLaunchKernelGGL(k_expand_heavy<kMultiRec>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+    else if (mode == kLe) hipLaunchKernelGGL(k_expand_heavy<kLe>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else if (mode == kLdd) hipLaunchKernelGGL(k_expand_heavy<kLdd>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else if (mode == kMultiFirst) hipLaunchKernelGGL(k_expand_heavy<kMultiFirst>, dim3(hb), dim3(kBlock), 0, c->stream, P);
     else if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
@@ -694,14 +704,21 @@ void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
     S.label = L.S.label;
     S.srclab = L.S.srclab;
     S.first = L.S.first;
+    S.rec = L.S.rec;
     S.table = L.T->p;
     S.tmask = ts - 1;
     L.S = S;
     // the abandoned attempt's first-source claims go too
     if (S.first) fill_u32(c, (uint32_t *)S.first, (uint64_t)P.n, 0xffffffffu);
+    if (S.rec) {
+        hipLaunchKernelGGL(k_clear_rec_slots, dim3(grid_for(c, (uint64_t)P.n)), dim3(kBlock), 0, c->stream,
+                           (int32_t)P.n, S.rec);
+        LAUNCHCHK("k_clear_rec_slots");
+    }
     SeedArgs A;
     memset(&A, 0, sizeof A);
-    A.first[0] = S.first;
+    A.first[0] = S.rec ? reinterpret_cast<int32_t *>(S.rec) + 3 : S.first;
+    A.fstride[0] = S.rec ? 4 : 1;
     A.T[0] = S.table;
     A.mask[0] = S.tmask;
     A.F[0] = S.F;
@@ -1223,6 +1240,20 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     LAUNCHCHK("k_finish_single");
     phase_end(c, ph);
     if (st && j1 < (uint32_t)n) st->batches = 1;
+    // packed records for the multi-source batches (first-source slots on):
+    // worth their build pass (32 bytes per vertex written) when most
+    // vertices survived trimming; not in the allocation-free path
+    const bool use_rec = use_first && !c->noalloc &&
+                         (o.packed == 1 || (o.packed == -1 && 2 * ((int64_t)n - trimmed) > (int64_t)n));
+    if (use_rec) {
+        phase_begin(c, 4, ph);
+        ensure(c, c->rec[0], (uint64_t)n);
+        ensure(c, c->rec[1], (uint64_t)n);
+        hipLaunchKernelGGL(k_build_rec, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g.out_off,
+                           g.in_off, c->label.p, c->rec[0].p, c->rec[1].p);
+        LAUNCHCHK("k_build_rec");
+        phase_end(c, ph);
+    }
 
     // ---- multi-source batches (Algorithm 1, prefix doubling with beta).  The
     // host's view of |V'| lags one batch behind (it is read at the next
@@ -1234,7 +1265,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     int32_t epoch = 1;
     int32_t stamp_ep = c->stamp_next;  // owner-election stamp of the current batch
     bool invp_built = false;  // the inverse permutation of this call's P is stored
-    uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0;
+    uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0, at_out = 0, at_in = 0;
     int64_t active = (int64_t)n - trimmed;  // upper bound
     while (active > 0 && pos < (uint64_t)n) {
         // Batches grow by beta (Algorithm 1), or by beta_fast after a batch
@@ -1277,9 +1308,11 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         // more pairs restarts on a larger table, instead of every batch
         // reserving tables (and the frontier bags sized from them) for the
         // worst case.
+        // (with first-source slots, a counts the previous batch's table pairs
+        // and the floor is an eighth: most pairs sit in the slots)
         auto size_for = [&](uint64_t a) {
-            uint64_t want = (uint64_t)std::max((double)o.table_floor * (double)active,
-                                               1.5 * growth * (double)a);
+            const double floor = (double)o.table_floor * (double)active / (use_first ? 8.0 : 1.0);
+            uint64_t want = (uint64_t)std::max(floor, 1.5 * growth * (double)a);
             want = std::min<uint64_t>(want, 8 * (uint64_t)std::max<int64_t>(active, 0) + 2 * kmax);
             want = std::max<uint64_t>(want, 2 * kmax);
             want = std::min<uint64_t>(want, c->table_slots_max);
@@ -1288,8 +1321,8 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             return next_pow2(want);
         };
         auto t_rs = std::chrono::steady_clock::now();
-        ts_out = size_for(a_out);
-        ts_in = size_for(a_in);
+        ts_out = size_for(use_first ? at_out : a_out);
+        ts_in = size_for(use_first ? at_in : a_in);
         bool grew = false;
         ensure(c, c->Tout, ts_out, &grew);
         if (grew) fill_u64(c, c->Tout.p, c->Tout.cap, kEmpty64);
@@ -1309,13 +1342,15 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             uint64_t &ts = d ? ts_in : ts_out;
             L[d] = Lane();
             L[d].id = d;
-            L[d].mode = use_first ? kMultiFirst : kMulti;
+            L[d].mode = use_rec ? kMultiRec : (use_first ? kMultiFirst : kMulti);
             L[d].n = n;
             L[d].T = &T;
             L[d].tslots = &ts;
             L[d].S = make_search(c, d, o, L[d].mode);
-            L[d].S.first = use_first ? c->firstS[d].p : nullptr;
-            SA.first[d] = L[d].S.first;
+            L[d].S.first = (use_first && !use_rec) ? c->firstS[d].p : nullptr;
+            L[d].S.rec = use_rec ? c->rec[d].p : nullptr;
+            SA.first[d] = use_rec ? reinterpret_cast<int32_t *>(c->rec[d].p) + 3 : L[d].S.first;
+            SA.fstride[d] = use_rec ? 4 : 1;
             L[d].S.off = d ? g.in_off : g.out_off;
             L[d].S.adj = d ? g.in_adj : g.out_adj;
             L[d].S.label = c->label.p;
@@ -1339,6 +1374,11 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         const uint32_t k = c->hctl->sh.k;
         a_out = c->hctl->lane[0].claims + k;
         a_in = c->hctl->lane[1].claims + k;
+        // with first-source slots the tables hold only the later pairs of a
+        // vertex: the next tables are sized from those
+        at_out = c->hctl->lane[0].tclaims;
+        at_in = c->hctl->lane[1].tclaims;
+        if (st) st->claims_table += (int64_t)(at_out + at_in);
         // a cheap batch: its frontiers never used a sixteenth of the GPU's
         // lanes (its rounds were latency bound), or its sources reached few
         // vertices each and its frontiers never filled the GPU; the next
@@ -1360,15 +1400,24 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         // (first-source slots are read per vertex, so such batches always
         // take the per-vertex relabel)
         const bool dense_label = use_first || (a_out + a_in) * kDenseLabelDiv >= (uint64_t)n;
-        int32_t *fF = use_first ? c->firstS[0].p : nullptr, *fB = use_first ? c->firstS[1].p : nullptr;
+        int32_t *fF = nullptr, *fB = nullptr;
+        const int32_t fstride = use_rec ? 4 : 1;
+        if (use_rec) {
+            fF = reinterpret_cast<int32_t *>(c->rec[0].p) + 3;
+            fB = reinterpret_cast<int32_t *>(c->rec[1].p) + 3;
+        } else if (use_first) {
+            fF = c->firstS[0].p;
+            fB = c->firstS[1].p;
+        }
         hipLaunchKernelGGL(k_accumulate, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p, ts_out - 1,
                            c->Tin.p, ts_in - 1, kProbeLimit, c->srcvert.p, c->sig_out.p, c->sig_in.p, c->fin.p,
-                           dense_label, fF, fB);
+                           dense_label, fF, fB, fstride);
         LAUNCHCHK("k_accumulate");
         if (dense_label) {
             hipLaunchKernelGGL(k_relabel_dense, dim3(grid_for(c, std::max<uint64_t>(ts_out, (uint64_t)n))), dim3(kBlock),
                                0, c->stream, n, c->Tout.p, ts_out - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p,
-                               c->fin.p, c->label.p, &c->dctl->cs, fF, fB);
+                               c->fin.p, c->label.p, &c->dctl->cs, fF, fB, fstride, use_rec ? c->rec[0].p : nullptr,
+                               use_rec ? c->rec[1].p : nullptr);
             LAUNCHCHK("k_relabel_dense");
         } else {
             hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p,
@@ -1433,52 +1482,74 @@ __global__ void k_check_sources(int32_t n, int32_t k, const int32_t *sources, co
     }
 }
 
-// Union CSR of a batch of graphs: global id = vtx_base[g] + local id.
+// Union CSR of a batch of graphs: global id = vtx_base[g] + local id.  The
+// element range is cut into tiles of kUnionTile; one thread finds the graph
+// of the tile's first element by binary search over the bases, and every
+// thread then walks forward from it (a tile spans few graphs), so the pass
+// streams the arrays instead of searching per element.
+constexpr int64_t kUnionTile = 4096;
+
+// The graph of element x among graphs [g0, g0 + G): the last one whose base
+// (bases = vb or ab) is <= x.  One thread of the block; the result in LDS.
+__device__ __forceinline__ int32_t tile_graph(const int64_t *bases, int32_t g0, int32_t G, int64_t x) {
+    __shared__ int32_t gs;
+    if (threadIdx.x == 0) {
+        int32_t lo = g0, hi = g0 + G - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (bases[mid] <= x) lo = mid; else hi = mid - 1;
+        }
+        gs = lo;
+    }
+    __syncthreads();
+    const int32_t g = gs;
+    __syncthreads();  // gs is rewritten by the next tile
+    return g;
+}
+
 __global__ void k_union_off(int32_t G, const int64_t *vb, const int64_t *ab, const int32_t *off_in, int32_t *off_out,
                             int64_t arc0, int32_t g0) {
     const int64_t v0 = vb[g0];
     const int64_t nv = vb[g0 + G] - v0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= nv; i += (int64_t)gridDim.x * blockDim.x) {
-        if (i == nv) {
-            off_out[i] = (int32_t)(ab[g0 + G] - arc0);
-            continue;
+    for (int64_t t0 = (int64_t)blockIdx.x * kUnionTile; t0 <= nv; t0 += (int64_t)gridDim.x * kUnionTile) {
+        int32_t g = tile_graph(vb, g0, G, v0 + (t0 < nv ? t0 : nv - 1));
+        const int64_t t1 = t0 + kUnionTile < nv + 1 ? t0 + kUnionTile : nv + 1;
+        for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+            if (i == nv) {
+                off_out[i] = (int32_t)(ab[g0 + G] - arc0);
+                continue;
+            }
+            const int64_t gv = v0 + i;
+            while (vb[g + 1] <= gv) g++;
+            off_out[i] = (int32_t)(ab[g] - arc0 + off_in[vb[g] + g + (gv - vb[g])]);
         }
-        // graph of vertex i: the last graph whose base is <= its global id
-        int lo = g0, hi = g0 + G - 1;
-        const int64_t gv = v0 + i;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (vb[mid] <= gv) lo = mid; else hi = mid - 1;
-        }
-        const int64_t local = gv - vb[lo];
-        off_out[i] = (int32_t)(ab[lo] - arc0 + off_in[vb[lo] + lo + local]);
     }
 }
 __global__ void k_union_adj(int32_t G, const int64_t *vb, const int64_t *ab, const int32_t *adj_in, int32_t *adj_out,
                             int32_t g0) {
     const int64_t a0 = ab[g0];
     const int64_t na = ab[g0 + G] - a0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < na; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t ge = a0 + e;
-        int lo = g0, hi = g0 + G - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (ab[mid] <= ge) lo = mid; else hi = mid - 1;
+    for (int64_t t0 = (int64_t)blockIdx.x * kUnionTile; t0 < na; t0 += (int64_t)gridDim.x * kUnionTile) {
+        int32_t g = tile_graph(ab, g0, G, a0 + t0);
+        const int64_t t1 = t0 + kUnionTile < na ? t0 + kUnionTile : na;
+        for (int64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+            const int64_t ge = a0 + e;
+            while (ab[g + 1] <= ge) g++;
+            adj_out[e] = (int32_t)(vb[g] - vb[g0] + adj_in[ge]);
         }
-        adj_out[e] = (int32_t)(vb[lo] - vb[g0] + adj_in[ge]);
     }
 }
 __global__ void k_union_labels(int32_t G, const int64_t *vb, const int32_t *lab_in, int32_t *lab_out, int32_t g0) {
     const int64_t v0 = vb[g0];
     const int64_t nv = vb[g0 + G] - v0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
-        int lo = g0, hi = g0 + G - 1;
-        const int64_t gv = v0 + i;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (vb[mid] <= gv) lo = mid; else hi = mid - 1;
+    for (int64_t t0 = (int64_t)blockIdx.x * kUnionTile; t0 < nv; t0 += (int64_t)gridDim.x * kUnionTile) {
+        int32_t g = tile_graph(vb, g0, G, v0 + t0);
+        const int64_t t1 = t0 + kUnionTile < nv ? t0 + kUnionTile : nv;
+        for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+            const int64_t gv = v0 + i;
+            while (vb[g + 1] <= gv) g++;
+            lab_out[gv] = (int32_t)(lab_in[i] + v0 - vb[g]);
         }
-        lab_out[gv] = (int32_t)(lab_in[i] + v0 - vb[lo]);
     }
 }
 
@@ -1517,6 +1588,7 @@ void accumulate_stats(scc_stats_t &acc, const scc_stats_t &st) {
     acc.arcs_scanned += st.arcs_scanned;
     acc.claim_attempts += st.claim_attempts;
     acc.claims += st.claims;
+    acc.claims_table += st.claims_table;
     acc.bag_inserts += st.bag_inserts;
     acc.bag_chunk_advances += st.bag_chunk_advances;
     acc.table_restarts += st.table_restarts;
@@ -1711,7 +1783,7 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
         // one resident wave of blocks per expand variant: its waves take the
         // frontier's groups statically, so blocks beyond the resident set
         // would run a second, serial local search
-        for (int m = 0; m < 5; m++)
+        for (int m = 0; m < 6; m++)
             for (int ai = 0; ai < 3; ai++) {
                 int b = 0;
                 HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, expand_kernel(m, 1 << ai), kBlock, 0));
@@ -1748,7 +1820,7 @@ void scc_destroy(scc_ctx_t *c) {
         release(c->F[i]); release(c->heavy[i]); release(c->bag_slots[i]); release(c->bag_cnt[i]);
     }
     release(c->Tout); release(c->Tin); release(c->ubuf);
-    release(c->firstS[0]); release(c->firstS[1]);
+    release(c->firstS[0]); release(c->firstS[1]); release(c->rec[0]); release(c->rec[1]);
     release(c->rkeys[0]); release(c->rkeys[1]); release(c->rtemp); release(c->bstart);
     for (int i = 0; i < 2; i++) { release(c->lk[i]); release(c->gk[i]); release(c->ld[i]); release(c->gd[i]); }
     release(c->lkeep);
@@ -2035,7 +2107,11 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
             const uint64_t need = 2 * ((uint64_t)nv + 1) + 2 * (uint64_t)na + (uint64_t)nv;
             ensure(c, c->ubuf, need);
             int32_t *uo = c->ubuf.p, *ui = uo + nv + 1, *ua = ui + nv + 1, *uia = ua + na, *ul = uia + na;
-            const unsigned gv = grid_for(c, (uint64_t)nv + 1), ga = grid_for(c, (uint64_t)std::max<int64_t>(na, 1));
+            auto tiles = [&](uint64_t x) {
+                return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((x + kUnionTile - 1) / kUnionTile,
+                                                                         (uint64_t)c->num_cu * 8));
+            };
+            const unsigned gv = tiles((uint64_t)nv + 1), ga = tiles((uint64_t)std::max<int64_t>(na, 1));
             hipLaunchKernelGGL(k_union_off, dim3(gv), dim3(kBlock), 0, c->stream, cnt, dvb.p, dab.p, out_off, uo,
                                arc_base[g0], g0);
             hipLaunchKernelGGL(k_union_off, dim3(gv), dim3(kBlock), 0, c->stream, cnt, dvb.p, dab.p, in_off, ui,
@@ -2049,7 +2125,7 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
             scc_stats_t st;
             init_call(c, stats ? &st : nullptr, nv, na, &o);
             run_scc(c, gd, ul, o, stats ? &st : nullptr);
-            hipLaunchKernelGGL(k_union_labels, dim3(grid_for(c, (uint64_t)nv)), dim3(kBlock), 0, c->stream, cnt, dvb.p, ul,
+            hipLaunchKernelGGL(k_union_labels, dim3(tiles((uint64_t)nv)), dim3(kBlock), 0, c->stream, cnt, dvb.p, ul,
                                labels_out, g0);
             LAUNCHCHK("k_union_labels");
             HIPCHK(hipStreamSynchronize(c->stream));

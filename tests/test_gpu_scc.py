@@ -67,11 +67,12 @@ def test_quadratic_reach(gpu, opt):
     assert st["restart_rounds"] <= st["rounds_multi"]
 
 
-@pytest.mark.parametrize("first", [0, 1])
-def test_first_slot_families(gpu, first):
-    # the inline first-source slot on every family, including pair-heavy
-    # batches (the quadratic-reach graph) and restarts on a tiny table
-    opts = gpu.default_options(first_slot=first)
+@pytest.mark.parametrize("first,packed", [(0, 0), (1, 0), (1, 1)])
+def test_first_slot_families(gpu, first, packed):
+    # the inline first-source slot (separate or in packed records) on every
+    # family, including pair-heavy batches (the quadratic-reach graph) and
+    # restarts on a tiny table
+    opts = gpu.default_options(first_slot=first, packed=packed)
     for g in (graphgen.rmat(13, 16, seed=61), graphgen.knn(40000, 4, 5, 0.01, seed=62),
               graphgen.grid(150, 160, 0.5, seed=63), graphgen.lattice_oriented(60, 70, 1, seed=64)):
         check_labels(gpu, g, opts, name="%s first_slot=%d" % (g.name, first))
@@ -79,11 +80,12 @@ def test_first_slot_families(gpu, first):
     i, j = np.triu_indices(m, 1)
     g = graphgen.from_arcs(2 * m, np.concatenate([np.arange(m), np.arange(m) + m, i]),
                            np.concatenate([np.arange(m) + m, np.arange(m), j]))
-    check_labels(gpu, g, gpu.default_options(first_slot=first, beta=8.0), name="cycle-dag first_slot=%d" % first)
+    check_labels(gpu, g, gpu.default_options(first_slot=first, packed=packed, beta=8.0),
+                 name="cycle-dag first_slot=%d packed=%d" % (first, packed))
     n = 20000
     g = graphgen.from_arcs(n, np.arange(n - 1), np.arange(1, n))
-    st = check_labels(gpu, g, gpu.default_options(first_slot=first, table_init=1024, table_floor=0.0),
-                      name="path20000 small table first_slot=%d" % first)
+    st = check_labels(gpu, g, gpu.default_options(first_slot=first, packed=packed, table_init=1024, table_floor=0.0),
+                      name="path20000 small table first_slot=%d packed=%d" % (first, packed))
     if not first:
         assert st["table_restarts"] > 0
 
@@ -147,6 +149,8 @@ def test_config0_full_size(gpu):
     dict(table_init=1024), dict(trim=0), dict(seed=12345), dict(table_floor=0.0), dict(table_floor=0.3),
     dict(first_slot=1), dict(first_slot=1, tau=1), dict(first_slot=1, table_init=1024, table_floor=0.0),
     dict(first_slot=1, arcs_per_lane=2), dict(vgc_measure=1), dict(vgc_measure=1, tau=64, first_slot=1),
+    dict(packed=1), dict(packed=0), dict(packed=1, table_init=1024, table_floor=0.0), dict(packed=1, tau=1),
+    dict(packed=1, arcs_per_lane=4), dict(packed=1, graph_rounds=1),
 ])
 def test_schedule_invariance(gpu, opt):
     g = graphgen.torus(100, 120, 0.55, seed=77)
