@@ -97,7 +97,12 @@ typedef struct {
  *                batch's pairs x the batch growth.  Default 1.2: a sparser
  *                table means fewer linear-probing steps, each a dependent
  *                load and CAS on the GPU, and HBM is plentiful; a smaller
- *                floor risks restarts on a larger table.
+ *                floor risks restarts on a larger table.  With first-source
+ *                slots the table holds only a vertex's later pairs: the
+ *                floor is halved, the pair term counts (g - 1) x the previous
+ *                pairs + its table pairs (g the batch growth), a full table
+ *                restarts four times as large, and each batch that restarted
+ *                doubles the floor of the call's later batches (up to 16x).
  *   seeds_per_wave frontier entries a wavefront takes per fetch (1..64);
  *                0 = chosen from the frontier size.
  *   timing       bit mask over SCC_KERNEL_*: bit k brackets every launch of
@@ -221,8 +226,10 @@ typedef struct {
     /* with options.timing: for the frontier kernels (SCC_KERNEL_*) the summed
      * event time of their launches, the number of launches and their
      * algorithmic bytes.  Expand and edge-parallel: frontier entry 8,
-     * offsets 8 per expanded entry, 4 per scanned arc, 4 per claim attempt,
-     * 8 (multi) or 4 (single) per claim, 8 per bag insert.  Pull: visited and
+     * offsets 8 per expanded entry, per scanned arc 8 (multi: target id and
+     * its label) or 4 (single: target id), per claim attempt 8 (multi: a
+     * reach-record probe) or 4 (single: a visited word), per claim 8 or 4,
+     * 8 per bag insert.  Pull: visited and
      * next words (n/4), offsets 8 per unvisited vertex, 8 per scanned arc
      * (target id + frontier word).  ExtractAll: 24 per extracted entry (bag
      * slot read, frontier write, the entry's offsets for the degree sum).

@@ -457,6 +457,7 @@ struct Lane {
     // multi source
     DevBuf<uint64_t> *T = nullptr;
     uint64_t *tslots = nullptr;
+    uint64_t *fslots = nullptr;  // frontier entries its buffers hold (null: from tslots)
 };
 
 struct DriveParams {
@@ -467,6 +468,7 @@ struct DriveParams {
     scc_stats_t *st = nullptr;
     double *resize_ms = nullptr;
     uint64_t peak_fdeg = 0;  // out: largest frontier degree sum seen at a host check
+    uint32_t table_full = 0; // out: restarts caused by a full reach table
 };
 
 // ExtractAll grid: each block walks 256 stripes (16K slots) per step, and the
@@ -685,17 +687,26 @@ void run_graph_block(scc_ctx *c, Lane **sp, int nsp, int k) {
 }
 
 // A multi-source lane whose reach table or frontier buffers overflowed
-// restarts on a table twice as large, with buffers to match (Section 4.5
-// resizes once an insertion probes too often; the table cannot grow while
-// claims are in flight).
-void restart_multi(scc_ctx *c, Lane &L, const DriveParams &P) {
+// restarts with the one that ran out larger (Section 4.5 resizes once an
+// insertion probes too often; the table cannot grow while claims are in
+// flight).  A full table grows fourfold: the abandoned attempt's work is
+// lost, and reach counts are heavy tailed, so a second restart costs more than
+// the larger table.  A lane without its own frontier size sizes the buffers
+// from the table.
+void restart_multi(scc_ctx *c, Lane &L, DriveParams &P, bool table_full, bool lane_full) {
     auto t0 = std::chrono::steady_clock::now();
     uint64_t &ts = *L.tslots;
-    ts *= 2;
+    if (table_full) {
+        ts *= 4;
+        P.table_full++;
+    } else if (!L.fslots) {
+        ts *= 2;
+    }
+    if (lane_full && L.fslots) *L.fslots *= 2;
     bool grew = false;
     ensure(c, *L.T, ts, &grew);
     fill_u64(c, L.T->p, grew ? L.T->cap : ts, kEmpty64);
-    ensure_lane(c, L.id, std::max<uint64_t>(ts, (uint64_t)P.n), c->bag_lam_log2[L.id]);
+    ensure_lane(c, L.id, L.fslots ? *L.fslots : std::max<uint64_t>(ts, (uint64_t)P.n), c->bag_lam_log2[L.id]);
     reset_bag(c, L.id);
     reset_lane_ctl(c, L.id);
     Search S = make_search(c, L.id, *P.o, L.mode);
@@ -777,7 +788,7 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
     uint64_t launched = 0;
     uint64_t limit = (uint64_t)P.n + 64;
     for (int i = 0; i < nl; i++)
-        if (lanes[i].mode != kSingle) limit = std::max<uint64_t>(limit, 2 * *lanes[i].tslots + 64);
+        if (lanes[i].mode != kSingle) limit = std::max<uint64_t>(limit, (uint64_t)P.n + 2 * *lanes[i].tslots + 64);
     bool was_dense[2] = {false, false};
     for (;;) {
         bool any = false, watch = false;
@@ -882,13 +893,13 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
                 c->trace.insert(c->trace.end(), row, row + SCC_TRACE_FIELDS);
             }
             // a multi-source search whose reach table or frontier buffers ran
-            // out restarts with both doubled
+            // out restarts with the one that ran out doubled
             if (L.mode != kSingle && ((rc.err & kErrTable) || lane_full)) {
                 if (P.st) {
                     P.st->rounds_multi += rc.rounds;  // rounds of the abandoned attempt
                     P.st->restart_rounds += rc.rounds;
                 }
-                restart_multi(c, L, P);
+                restart_multi(c, L, P, (rc.err & kErrTable) != 0, lane_full);
                 L.fdeg = L.claims = 0;
                 L.rounds = 0;
                 L.policy_primed = false;
@@ -1110,9 +1121,12 @@ void fill_counters(scc_ctx *c, scc_stats_t *st, int64_t n) {
         st->ms_kernel[k] = c->tm_ms[k];
         st->launches_kernel[k] = c->tm_launches[k];
     }
+    // multi-source: every scanned arc reads its target and the target's
+    // label, every claim attempt probes 8 bytes and a claim writes 8;
+    // single-source: the visited bitmap word stands in for label and probe
     auto search_bytes = [&](int k, bool multi) {
         return (int64_t)(ctr_kind(cn, k, kCtrSeeds) * 8 + ctr_kind(cn, k, kCtrExpanded) * 8 +
-                         ctr_kind(cn, k, kCtrArcs) * 4 + ctr_kind(cn, k, kCtrAttempts) * 4 +
+                         ctr_kind(cn, k, kCtrArcs) * (multi ? 8 : 4) + ctr_kind(cn, k, kCtrAttempts) * (multi ? 8 : 4) +
                          ctr_kind(cn, k, kCtrClaims) * (multi ? 8 : 4) + ctr_kind(cn, k, kCtrInserts) * 8);
     };
     st->bytes_kernel[SCC_KERNEL_EXPAND_SINGLE] = search_bytes(kKindExpandSingle, false);
@@ -1265,7 +1279,8 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     int32_t epoch = 1;
     int32_t stamp_ep = c->stamp_next;  // owner-election stamp of the current batch
     bool invp_built = false;  // the inverse permutation of this call's P is stored
-    uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0, at_out = 0, at_in = 0;
+    uint64_t a_out = 0, a_in = 0, ts_out = 0, ts_in = 0, at_out = 0, at_in = 0, fs[2] = {0, 0};
+    double floor_boost = 1.0;
     int64_t active = (int64_t)n - trimmed;  // upper bound
     while (active > 0 && pos < (uint64_t)n) {
         // Batches grow by beta (Algorithm 1), or by beta_fast after a batch
@@ -1308,11 +1323,20 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         // more pairs restarts on a larger table, instead of every batch
         // reserving tables (and the frontier bags sized from them) for the
         // worst case.
-        // (with first-source slots, a counts the previous batch's table pairs
-        // and the floor is an eighth: most pairs sit in the slots)
-        auto size_for = [&](uint64_t a) {
-            const double floor = (double)o.table_floor * (double)active / (use_first ? 8.0 : 1.0);
-            uint64_t want = (uint64_t)std::max(floor, 1.5 * growth * (double)a);
+        // With first-source slots a vertex's first pair sits in its slot and
+        // only the others go to the table.  A batch g times larger finds about
+        // g times the pairs, on at least the vertices the previous batch
+        // reached (a - at of them, at = its table pairs), so the table is
+        // sized for (g - 1) a + at pairs, and the floor is half (the
+        // vertices' first pairs need no room).  Each batch whose table filled
+        // up doubles the floor of the call's later batches: one source
+        // reaching much more than the earlier ones did shows that the
+        // estimate is low for this graph.
+        auto size_for = [&](uint64_t a, uint64_t at) {
+            const double floor = (double)o.table_floor * (double)active * floor_boost / (use_first ? 2.0 : 1.0);
+            const double pairs = use_first ? std::max(growth - 1.0, 0.0) * (double)a + (double)at
+                                           : growth * (double)a;
+            uint64_t want = (uint64_t)std::max(floor, 1.5 * pairs);
             want = std::min<uint64_t>(want, 8 * (uint64_t)std::max<int64_t>(active, 0) + 2 * kmax);
             want = std::max<uint64_t>(want, 2 * kmax);
             want = std::min<uint64_t>(want, c->table_slots_max);
@@ -1321,19 +1345,25 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             return next_pow2(want);
         };
         auto t_rs = std::chrono::steady_clock::now();
-        ts_out = size_for(use_first ? at_out : a_out);
-        ts_in = size_for(use_first ? at_in : a_in);
+        ts_out = size_for(a_out, at_out);
+        ts_in = size_for(a_in, at_in);
+        // frontier buffers for one round's pairs: sized from all the pairs
+        // the batch is expected to find (a table with first-source slots
+        // holds only some of them), at least n and at most 2n (a search that
+        // needs more restarts with larger ones)
+        for (int d = 0; d < 2; d++) {
+            const double full = std::max((double)o.table_floor * (double)active,
+                                         1.5 * growth * (double)(d ? a_in : a_out));
+            const uint64_t want = use_first ? next_pow2((uint64_t)std::max(full, 1024.0)) : (d ? ts_in : ts_out);
+            fs[d] = std::max<uint64_t>(std::min<uint64_t>(want, 2 * (uint64_t)n), (uint64_t)n);
+        }
         bool grew = false;
         ensure(c, c->Tout, ts_out, &grew);
         if (grew) fill_u64(c, c->Tout.p, c->Tout.cap, kEmpty64);
         ensure(c, c->Tin, ts_in, &grew);
         if (grew) fill_u64(c, c->Tin.p, c->Tin.cap, kEmpty64);
         c->tables_dirty = true;
-        for (int d = 0; d < 2; d++)
-            // frontier buffers for one round's pairs: up to 2n (a search that
-            // needs more restarts with larger ones)
-            ensure_lane(c, d, std::max<uint64_t>(std::min<uint64_t>(d ? ts_in : ts_out, 2 * (uint64_t)n), (uint64_t)n),
-                        c->bag_lam_log2[d]);
+        for (int d = 0; d < 2; d++) ensure_lane(c, d, fs[d], c->bag_lam_log2[d]);
         resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_rs).count();
         SeedArgs SA;
         memset(&SA, 0, sizeof SA);
@@ -1346,6 +1376,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             L[d].n = n;
             L[d].T = &T;
             L[d].tslots = &ts;
+            L[d].fslots = &fs[d];
             L[d].S = make_search(c, d, o, L[d].mode);
             L[d].S.first = (use_first && !use_rec) ? c->firstS[d].p : nullptr;
             L[d].S.rec = use_rec ? c->rec[d].p : nullptr;
@@ -1368,8 +1399,10 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         LAUNCHCHK("k_seed_multi");
         DP.nsub = active;
         DP.peak_fdeg = 0;
+        DP.table_full = 0;
         c->epoch = epoch;
         drive(c, L, 2, DP);
+        if (DP.table_full) floor_boost = std::min(floor_boost * 2.0, 16.0);
         phase_end(c, ph);
         const uint32_t k = c->hctl->sh.k;
         a_out = c->hctl->lane[0].claims + k;
