@@ -111,6 +111,11 @@ constexpr uint32_t kErrCapacity = 2u;   // frontier / heavy list capacity exceed
 constexpr uint32_t kErrUnfinished = 4u; // a vertex had no SCC key at the end
 
 constexpr int kQcap = 256;  // local queue entries per wave (LDS)
+// First-source slot claims flag their vertex's granule of 2^kDirtyLog2
+// vertices (a plain byte store, nothing waits for it), so the per-vertex
+// relabel visits only granules that a batch touched: a vertex has table pairs
+// only if its slot is taken, and sums and finish marks only if it has pairs.
+constexpr int kDirtyLog2 = 12;
 constexpr int kQmask = kQcap - 1;
 constexpr int kStepArcs = 256;  // arcs a wave commits to per local-search step
 constexpr int kHeavyChunk = 4096;  // arcs per edge-parallel work item
@@ -139,6 +144,7 @@ struct Search {
     uint64_t *table;        // kMulti
     int32_t *first;         // kMultiFirst: per-vertex first-source slot (-1 = empty)
     int4 *rec;              // kMultiRec: per-vertex {first arc, degree, label, first-source slot}
+    uint8_t *dirty;         // first-source slots: granule flags (null: none kept)
     int32_t *owner;         // kLdd: cluster centre of each claimed vertex
     int32_t level;          // kLe: distance of the entries this round expands
     uint64_t tmask;
@@ -514,6 +520,7 @@ struct SeedArgs {
     uint64_t *T[2];
     int32_t *first[2];      // non-null: the lane claims first pairs in per-vertex slots
     int32_t fstride[2];     // their stride in int32 (1 plain slots, 4 packed records)
+    uint8_t *dirty;         // granule flags of claimed slots (may be null)
     uint64_t mask[2];
     uint64_t *F[2];
     RoundCtl *rc[2];
@@ -531,6 +538,7 @@ __global__ void k_seed_multi(const int32_t *srcvert, const Shared *sh, SeedArgs 
                                                    limit, srcvert[j], j)
                                  : claim_pair(A.T[l], A.mask[l], limit, key);
         if (c < 0) atomicOr(&rc->err, kErrTable);
+        if (c == 1 && A.first[l] && A.dirty) A.dirty[srcvert[j] >> kDirtyLog2] = 1;
         A.F[l][j] = key;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -844,7 +852,10 @@ __device__ __forceinline__ void expand_round(const Search &S, uint32_t bid, uint
                             } else if (fs[j] == -1) {
                                 int32_t *sl = REC ? reinterpret_cast<int32_t *>(S.rec + w[j]) + 3 : S.first + w[j];
                                 const int32_t old = atomicCAS(sl, -1, src);
-                                if (old == -1) st[j] = 1;
+                                if (old == -1) {
+                                    st[j] = 1;
+                                    if (S.dirty) S.dirty[w[j] >> kDirtyLog2] = 1;
+                                }
                                 else if (old == src) st[j] = 0;
                                 else tab[j] = true;
                             } else {
@@ -1046,6 +1057,7 @@ __device__ __forceinline__ void heavy_round(const Search &S, uint32_t bid, uint3
                     if (c < 0) atomicOr(&rc->err, kErrTable);
                     claimed = c >= 1;
                     c_tclaims += c == 2 ? 1 : 0;
+                    if (c == 1 && S.dirty) S.dirty[w >> kDirtyLog2] = 1;
                 }
                 ne = pair_key(w, src);
             }
@@ -1445,50 +1457,88 @@ __global__ void k_relabel_multi(uint64_t *Tout, uint64_t mout, uint64_t *Tin, ui
 // was touched iff its accumulators are set; finished vertices are never
 // claimed).  The forward table is cleared here, the backward one was cleared
 // by k_accumulate.
+__device__ __forceinline__ uint32_t relabel_vertex(uint64_t v, const int32_t *srcvert, unsigned long long *sig_out,
+                                                   unsigned long long *sig_in, int32_t *fin, int32_t *label,
+                                                   int32_t *firstF, int32_t *firstB, int32_t fstride, int4 *recF,
+                                                   int4 *recB) {
+    const int32_t l = label[v];
+    if (l < 0) return 0;
+    int32_t f = kInf32;
+    unsigned long long si = 0, so = 0;
+    if (firstF) {
+        // the first-source slots: their pairs join the signatures, a source
+        // in both slots finishes the vertex, and the slots empty; a vertex
+        // with both slots empty has no pairs at all (table pairs need a
+        // taken slot), so its accumulators are not read
+        int32_t *pa = firstF + (int64_t)fstride * v, *pb = firstB + (int64_t)fstride * v;
+        const int32_t a = *pa, b = *pb;
+        if (a < 0 && b < 0) return 0;
+        f = fin[v];
+        si = sig_in[v];
+        so = sig_out[v];
+        if (a >= 0) {
+            so += sig_term_out(srcvert[a]);
+            *pa = -1;
+        }
+        if (b >= 0) {
+            si += sig_term_in(srcvert[b]);
+            *pb = -1;
+        }
+        if (a >= 0 && a == b && a < f) f = a;
+    } else {
+        f = fin[v];
+        si = sig_in[v];
+        so = sig_out[v];
+    }
+    int32_t nl;
+    uint32_t fin_cnt = 0;
+    if (f != kInf32) {
+        nl = ~srcvert[f];
+        fin_cnt = 1;
+    } else if ((si | so) != 0ull) {
+        nl = relabel_hash(l, si, so);
+    } else {
+        return 0;
+    }
+    label[v] = nl;
+    if (recF) {  // the packed records carry a copy of the label
+        recF[v].z = nl;
+        recB[v].z = nl;
+    }
+    sig_in[v] = 0;
+    sig_out[v] = 0;
+    fin[v] = kInf32;
+    return fin_cnt;
+}
+
+// Multi source, pass 2 for batches whose pairs are a sizeable fraction of the
+// vertices: the same relabelling as k_relabel_multi, taken per vertex in one
+// coalesced pass instead of per table slot with an owner election (a vertex
+// was touched iff its accumulators are set; finished vertices are never
+// claimed).  With granule flags (first-source slots), only flagged granules
+// are visited, and their flags are cleared.  The forward table is cleared
+// here, the backward one was cleared by k_accumulate.
 __global__ void k_relabel_dense(int32_t n, uint64_t *Tout, uint64_t mout, const int32_t *srcvert,
                                 unsigned long long *sig_out, unsigned long long *sig_in, int32_t *fin, int32_t *label,
                                 CountStripes *cs, int32_t *firstF, int32_t *firstB, int32_t fstride, int4 *recF,
-                                int4 *recB) {
+                                int4 *recB, uint8_t *dirty) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= mout; i += stride) Tout[i] = kEmpty64;
     uint32_t cnt = 0;
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < (uint64_t)n; v += stride) {
-        const int32_t l = label[v];
-        if (l < 0) continue;
-        int32_t f = fin[v];
-        unsigned long long si = sig_in[v], so = sig_out[v];
-        if (firstF) {
-            // the first-source slots: their pairs join the signatures, a
-            // source in both slots finishes the vertex, and the slots empty
-            int32_t *pa = firstF + (int64_t)fstride * v, *pb = firstB + (int64_t)fstride * v;
-            const int32_t a = *pa, b = *pb;
-            if (a >= 0) {
-                so += sig_term_out(srcvert[a]);
-                *pa = -1;
-            }
-            if (b >= 0) {
-                si += sig_term_in(srcvert[b]);
-                *pb = -1;
-            }
-            if (a >= 0 && a == b && a < f) f = a;
+    if (!dirty) {
+        for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < (uint64_t)n; v += stride)
+            cnt += relabel_vertex(v, srcvert, sig_out, sig_in, fin, label, firstF, firstB, fstride, recF, recB);
+    } else {
+        const uint64_t ng = ((uint64_t)n + (1u << kDirtyLog2) - 1) >> kDirtyLog2;
+        for (uint64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+            const uint8_t d = dirty[g];
+            __syncthreads();  // every thread has read the flag before it is cleared
+            if (!d) continue;
+            if (threadIdx.x == 0) dirty[g] = 0;
+            const uint64_t v1 = min((g + 1) << kDirtyLog2, (uint64_t)n);
+            for (uint64_t v = (g << kDirtyLog2) + threadIdx.x; v < v1; v += blockDim.x)
+                cnt += relabel_vertex(v, srcvert, sig_out, sig_in, fin, label, firstF, firstB, fstride, recF, recB);
         }
-        int32_t nl;
-        if (f != kInf32) {
-            nl = ~srcvert[f];
-            cnt++;
-        } else if ((si | so) != 0ull) {
-            nl = relabel_hash(l, si, so);
-        } else {
-            continue;
-        }
-        label[v] = nl;
-        if (recF) {  // the packed records carry a copy of the label
-            recF[v].z = nl;
-            recB[v].z = nl;
-        }
-        sig_in[v] = 0;
-        sig_out[v] = 0;
-        fin[v] = kInf32;
     }
     block_add_u32(&cs->s[blockIdx.x % kStripes].fin, cnt);
 }

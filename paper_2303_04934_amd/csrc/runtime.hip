@@ -85,6 +85,7 @@ struct scc_ctx {
     DevBuf<uint64_t> Tout, Tin;     // reach tables (forward, backward)
     DevBuf<int32_t> firstS[2];      // first-source slots per direction (options.first_slot)
     DevBuf<int4> rec[2];            // packed per-vertex records per direction (options.packed)
+    DevBuf<uint8_t> dirty;          // granules with a claimed first-source slot (kept all clear between batches)
     int64_t first_clean_n = 0;      // the slots are known empty (-1) on [0, first_clean_n)
     DevBuf<uint64_t> F[2], heavy[2];
     DevBuf<uint64_t> bag_slots[2];
@@ -716,6 +717,7 @@ void restart_multi(scc_ctx *c, Lane &L, DriveParams &P, bool table_full, bool la
     S.srclab = L.S.srclab;
     S.first = L.S.first;
     S.rec = L.S.rec;
+    S.dirty = L.S.dirty;
     S.table = L.T->p;
     S.tmask = ts - 1;
     L.S = S;
@@ -728,6 +730,7 @@ void restart_multi(scc_ctx *c, Lane &L, DriveParams &P, bool table_full, bool la
     }
     SeedArgs A;
     memset(&A, 0, sizeof A);
+    A.dirty = S.dirty;
     A.first[0] = S.rec ? reinterpret_cast<int32_t *>(S.rec) + 3 : S.first;
     A.fstride[0] = S.rec ? 4 : 1;
     A.T[0] = S.table;
@@ -1269,6 +1272,16 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         phase_end(c, ph);
     }
 
+    // granule flags of claimed first-source slots (all clear between batches)
+    uint8_t *dirty = nullptr;
+    if (use_first && !c->noalloc) {
+        bool grew = false;
+        const uint64_t ng = (((uint64_t)n + (1u << kDirtyLog2) - 1) >> kDirtyLog2) + 4;
+        ensure(c, c->dirty, ng, &grew);
+        if (grew) fill_u32(c, reinterpret_cast<uint32_t *>(c->dirty.p), c->dirty.cap / 4, 0u);
+        dirty = c->dirty.p;
+    }
+
     // ---- multi-source batches (Algorithm 1, prefix doubling with beta).  The
     // host's view of |V'| lags one batch behind (it is read at the next
     // check); it is only used as an upper bound.
@@ -1380,8 +1393,10 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             L[d].S = make_search(c, d, o, L[d].mode);
             L[d].S.first = (use_first && !use_rec) ? c->firstS[d].p : nullptr;
             L[d].S.rec = use_rec ? c->rec[d].p : nullptr;
+            L[d].S.dirty = dirty;
             SA.first[d] = use_rec ? reinterpret_cast<int32_t *>(c->rec[d].p) + 3 : L[d].S.first;
             SA.fstride[d] = use_rec ? 4 : 1;
+            SA.dirty = dirty;
             L[d].S.off = d ? g.in_off : g.out_off;
             L[d].S.adj = d ? g.in_adj : g.out_adj;
             L[d].S.label = c->label.p;
@@ -1450,7 +1465,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
             hipLaunchKernelGGL(k_relabel_dense, dim3(grid_for(c, std::max<uint64_t>(ts_out, (uint64_t)n))), dim3(kBlock),
                                0, c->stream, n, c->Tout.p, ts_out - 1, c->srcvert.p, c->sig_out.p, c->sig_in.p,
                                c->fin.p, c->label.p, &c->dctl->cs, fF, fB, fstride, use_rec ? c->rec[0].p : nullptr,
-                               use_rec ? c->rec[1].p : nullptr);
+                               use_rec ? c->rec[1].p : nullptr, dirty);
             LAUNCHCHK("k_relabel_dense");
         } else {
             hipLaunchKernelGGL(k_relabel_multi, dim3(grid_for(c, tot)), dim3(kBlock), 0, c->stream, c->Tout.p,
@@ -1853,7 +1868,7 @@ void scc_destroy(scc_ctx_t *c) {
         release(c->F[i]); release(c->heavy[i]); release(c->bag_slots[i]); release(c->bag_cnt[i]);
     }
     release(c->Tout); release(c->Tin); release(c->ubuf);
-    release(c->firstS[0]); release(c->firstS[1]); release(c->rec[0]); release(c->rec[1]);
+    release(c->firstS[0]); release(c->firstS[1]); release(c->rec[0]); release(c->rec[1]); release(c->dirty);
     release(c->rkeys[0]); release(c->rkeys[1]); release(c->rtemp); release(c->bstart);
     for (int i = 0; i < 2; i++) { release(c->lk[i]); release(c->gk[i]); release(c->ld[i]); release(c->gd[i]); }
     release(c->lkeep);
