@@ -57,16 +57,28 @@ KERNEL_SHORT = ["k_expand0", "k_expand1", "k_pull", "k_heavy0", "k_heavy1", "k_e
 NK = len(KERNEL_SHORT)
 
 
-def kernel_name(kind, app="scc", first_slot=1):
+def kernel_name(kind, app="scc", first_slot=1, packed=False):
     """rocprofv3's name of the kernel that timing kind `kind` brackets: the
     expand and edge-parallel kernels are instantiated per search mode (0
     single source, 1 multi-source, 2 multi-source with first-source slots,
-    3 LDD of connectivity, 4 LE-lists BFS)."""
+    3 LDD of connectivity, 4 LE-lists BFS, 5 first-source slots in packed
+    per-vertex records)."""
     single = {"scc": 0, "cc": 3, "le": 0}[app]
-    multi = {"scc": 2 if first_slot else 1, "cc": 1, "le": 4}[app]
+    multi = {"scc": (5 if packed else 2) if first_slot else 1, "cc": 1, "le": 4}[app]
     return ["hipscc::k_expand<%d, 1>" % single, "hipscc::k_expand<%d, 1>" % multi, "hipscc::k_pull",
             "hipscc::k_expand_heavy<%d>" % single, "hipscc::k_expand_heavy<%d>" % multi, "hipscc::k_bag_extract",
             "hipscc::k_cc_union"][kind]
+
+
+def packed_used(opts, st):
+    """Whether a call ran its multi-source batches on packed records: the
+    library's rule (options.packed = -1: when more than half the vertices
+    survive trimming), from the call's statistics."""
+    if not opts.first_slot or opts.packed == 0:
+        return False
+    return opts.packed == 1 or 2 * (st["n"] - st["trimmed"]) > st["n"]
+
+
 CPU_POOL = 16  # host threads for the multicore oracle (the CPU share of one GPU)
 
 
@@ -333,7 +345,8 @@ def run_batched(args, desc):
     ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
     la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
     by_k = [sum(s["bytes_kernel"][i] for s in stats) for i in range(NK)]
-    rf = roofline(ms_k, la_k, by_k, dom, "batched4096", kernel_name(dom, "scc", opts.first_slot))
+    rf = roofline(ms_k, la_k, by_k, dom, "batched4096",
+                  kernel_name(dom, "scc", opts.first_slot, packed_used(opts, stats[-1])))
     if rf:
         rf["launches_per_step"] = la_k[dom] / args.steps
         rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)
@@ -410,7 +423,8 @@ def run_single(args, cfg, desc):
     ms_k = [sum(s["ms_kernel"][i] for s in stats) for i in range(NK)]
     la_k = [sum(s["launches_kernel"][i] for s in stats) for i in range(NK)]
     by_k = [sum(s["bytes_kernel"][i] for s in stats) for i in range(NK)]
-    rf = roofline(ms_k, la_k, by_k, dom, args.workload, kernel_name(dom, "scc", opts.first_slot))
+    rf = roofline(ms_k, la_k, by_k, dom, args.workload,
+                  kernel_name(dom, "scc", opts.first_slot, packed_used(opts, stats[-1])))
     if rf:
         rf["launches_per_step"] = la_k[dom] / args.steps
         rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)

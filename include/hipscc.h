@@ -158,7 +158,16 @@ typedef struct {
  *                same round count and launch arguments comes again (cached
  *                per context); 0 (default) = one launch per kernel.  Not
  *                with timing, trace or the learned policy, and ignored by
- *                scc_labels_static. */
+ *                scc_labels_static.
+ *   union_streams  scc_labels_batched: the batch is split into at least this
+ *                many disjoint unions of consecutive graphs (balanced by
+ *                arcs), run concurrently, each on a stream of its own driven
+ *                by a host thread of its own (its state kept in a worker
+ *                context that the calling context owns); long-diameter
+ *                graphs leave most of the GPU idle in their latency-bound
+ *                rounds, which the other unions' rounds then use.  1 = the
+ *                unions run one after another on the context's stream; 0
+ *                (default) = automatic (2). */
 typedef struct {
     int32_t tau;
     float beta;
@@ -185,6 +194,7 @@ typedef struct {
     float ldd_beta;
     int32_t graph_rounds;
     int32_t packed;
+    int32_t union_streams;
 } scc_options_t;
 
 /* Frontier kernels timed with options.timing. */

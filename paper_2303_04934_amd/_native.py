@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
                 ("arcs_per_lane", ctypes.c_int32), ("vgc_fill", ctypes.c_float),
                 ("beta_fast", ctypes.c_float), ("table_floor", ctypes.c_float), ("union_arcs_max", ctypes.c_int32),
                 ("first_slot", ctypes.c_int32), ("vgc_measure", ctypes.c_int32), ("ldd_beta", ctypes.c_float),
-                ("graph_rounds", ctypes.c_int32), ("packed", ctypes.c_int32)]
+                ("graph_rounds", ctypes.c_int32), ("packed", ctypes.c_int32),
+                ("union_streams", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

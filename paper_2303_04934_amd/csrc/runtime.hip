@@ -19,6 +19,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -61,7 +62,9 @@ constexpr uint32_t kProbeLimit = 128;
 constexpr uint64_t kCheapPairs = 4;  // reach pairs per source of a batch that counts as cheap
 constexpr uint64_t kDenseLabelDiv = 8;
 constexpr int64_t kShortRounds = 4;      // a batch of at most this many rounds per direction is short ...
-constexpr double kShortGrowth = 64.0;    // ... and the next one grows by this factor  // relabel per vertex once a batch has n / 8 pairs
+constexpr double kShortGrowth = 64.0;
+constexpr int kMaxUnionStreams = 8;      // concurrent unions of scc_labels_batched
+constexpr int kAutoUnionStreams = 2;    // ... and the next one grows by this factor  // relabel per vertex once a batch has n / 8 pairs
 
 }  // namespace
 
@@ -129,6 +132,10 @@ struct scc_ctx {
     size_t pev_used = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> plog;
     Policy policy;
+    // scc_labels_batched with concurrent unions: one context per stream,
+    // owned by this one (created on first use, destroyed with it)
+    std::vector<scc_ctx *> workers;
+    size_t worker_groups = 0;       // unions of the workers' last batch
     // scc_labels_static: this device's copy of the static scratch array, and
     // whether the current call must not allocate (buffers are carved views)
     uint8_t *scratch = nullptr;
@@ -316,6 +323,7 @@ scc_options_t defaults() {
     o.ldd_beta = 1.2f;
     o.first_slot = 1;
     o.packed = -1;
+    o.union_streams = 0;
     return o;
 }
 
@@ -365,6 +373,10 @@ void check_opts(scc_ctx *c, const scc_options_t &o) {
     if (o.first_slot < 0 || o.first_slot > 1) { set_err(c, "first_slot must be 0 or 1"); throw Fail{SCC_EINVAL}; }
     if (o.vgc_measure < 0 || o.vgc_measure > 1) { set_err(c, "vgc_measure must be 0 or 1"); throw Fail{SCC_EINVAL}; }
     if (o.packed < -1 || o.packed > 1) { set_err(c, "packed must be -1, 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (o.union_streams < 0 || o.union_streams > kMaxUnionStreams) {
+        set_err(c, "union_streams must be in [0, %d]", kMaxUnionStreams);
+        throw Fail{SCC_EINVAL};
+    }
     if (!(o.ldd_beta > 1.0f) || !(o.ldd_beta < 1e6f)) { set_err(c, "ldd_beta must be > 1"); throw Fail{SCC_EINVAL}; }
 }
 
@@ -1857,24 +1869,37 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
     return SCC_OK;
 }
 
-void scc_destroy(scc_ctx_t *c) {
-    if (!c) return;
-    (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+// Frees every per-graph device buffer of a context (the next call allocates
+// what it needs again); the caller has synchronised its stream.
+void release_work_buffers(scc_ctx *c) {
     release(c->label); release(c->aux); release(c->stamp); release(c->invp); release(c->srcvert); release(c->srclab);
     release(c->fin); release(c->sig_out); release(c->sig_in);
     for (int i = 0; i < 2; i++) {
         release(c->vis[i]); release(c->bm[i][0]); release(c->bm[i][1]);
         release(c->F[i]); release(c->heavy[i]); release(c->bag_slots[i]); release(c->bag_cnt[i]);
+        c->bag_nchunks[i] = 0;
+        c->bag_lam_log2[i] = 0;
     }
     release(c->Tout); release(c->Tin); release(c->ubuf);
     release(c->firstS[0]); release(c->firstS[1]); release(c->rec[0]); release(c->rec[1]); release(c->dirty);
+    c->first_clean_n = 0;
     release(c->rkeys[0]); release(c->rkeys[1]); release(c->rtemp); release(c->bstart);
     for (int i = 0; i < 2; i++) { release(c->lk[i]); release(c->gk[i]); release(c->ld[i]); release(c->gd[i]); }
     release(c->lkeep);
-    policy_release(c->policy);
+    c->tables_dirty = false;
+    c->vclean_n = 0;
     for (auto &e : c->gcache) (void)hipGraphExecDestroy(e.second);
     c->gcache.clear();
+}
+
+void scc_destroy(scc_ctx_t *c) {
+    if (!c) return;
+    for (scc_ctx *w : c->workers) scc_destroy(w);
+    c->workers.clear();
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release_work_buffers(c);
+    policy_release(c->policy);
     if (c->dctl) (void)hipFree(c->dctl);
     if (c->hctl) (void)hipHostFree(c->hctl);
     for (auto &a : c->tev)
@@ -2141,13 +2166,30 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
         HIPCHK(hipMemcpyAsync(dab.p, arc_base, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, c->stream));
         // groups of consecutive graphs whose union has < 2^31 arcs; the
         // disjoint union of a group is one digraph whose SCCs are the graphs'
-        scc_stats_t acc;
-        memset(&acc, 0, sizeof acc);
-        int32_t g0 = 0;
         const int64_t lim = o.union_arcs_max > 0 ? (int64_t)o.union_arcs_max : (1ll << 31) - 1;
-        while (g0 < G) {
-            int32_t g1 = g0 + 1;
-            while (g1 < G && arc_base[g1 + 1] - arc_base[g0] < lim) g1++;
+        const int nstreams = o.union_streams > 0 ? o.union_streams : kAutoUnionStreams;
+        std::vector<std::pair<int32_t, int32_t>> groups;
+        {
+            // at least nstreams groups (when there are that many graphs),
+            // each closed once it holds its share of the arcs
+            int64_t parts = std::max<int64_t>((arc_base[G] + lim - 1) / lim, nstreams);
+            parts = std::min<int64_t>(parts, G);
+            const int64_t share = (arc_base[G] + parts - 1) / std::max<int64_t>(parts, 1);
+            int32_t g0 = 0;
+            while (g0 < G) {
+                int32_t g1 = g0 + 1;
+                while (g1 < G && arc_base[g1 + 1] - arc_base[g0] < lim && arc_base[g1] - arc_base[g0] < share &&
+                       (int64_t)groups.size() + 1 < parts)
+                    g1++;
+                if ((int64_t)groups.size() + 1 >= parts)  // the last part takes the rest, up to the arc limit
+                    while (g1 < G && arc_base[g1 + 1] - arc_base[g0] < lim) g1++;
+                groups.push_back({g0, g1});
+                g0 = g1;
+            }
+        }
+        // one union on context c (its stream, its buffers; the parameter
+        // hides the calling context, so errors are reported on c)
+        auto run_union = [&](scc_ctx *c, int32_t g0, int32_t g1, scc_stats_t *acc) {
             const int32_t cnt = g1 - g0;
             const int64_t nv = vtx_base[g1] - vtx_base[g0];
             const int64_t na = arc_base[g1] - arc_base[g0];
@@ -2165,20 +2207,105 @@ scc_status scc_labels_batched(scc_ctx_t *c, int32_t G, const int64_t *vtx_base, 
             hipLaunchKernelGGL(k_union_off, dim3(gv), dim3(kBlock), 0, c->stream, cnt, dvb.p, dab.p, in_off, ui,
                                arc_base[g0], g0);
             if (na > 0) {
-                hipLaunchKernelGGL(k_union_adj, dim3(ga), dim3(kBlock), 0, c->stream, cnt, dvb.p, dab.p, out_adj, ua, g0);
-                hipLaunchKernelGGL(k_union_adj, dim3(ga), dim3(kBlock), 0, c->stream, cnt, dvb.p, dab.p, in_adj, uia, g0);
+                hipLaunchKernelGGL(k_union_adj, dim3(ga), dim3(kBlock), 0, c->stream, cnt, dvb.p, dab.p, out_adj, ua,
+                                   g0);
+                hipLaunchKernelGGL(k_union_adj, dim3(ga), dim3(kBlock), 0, c->stream, cnt, dvb.p, dab.p, in_adj, uia,
+                                   g0);
             }
             LAUNCHCHK("k_union_*");
             GraphDev gd{(int32_t)nv, (int32_t)na, uo, ua, ui, uia};
             scc_stats_t st;
-            init_call(c, stats ? &st : nullptr, nv, na, &o);
-            run_scc(c, gd, ul, o, stats ? &st : nullptr);
+            init_call(c, acc ? &st : nullptr, nv, na, &o);
+            run_scc(c, gd, ul, o, acc ? &st : nullptr);
             hipLaunchKernelGGL(k_union_labels, dim3(tiles((uint64_t)nv)), dim3(kBlock), 0, c->stream, cnt, dvb.p, ul,
                                labels_out, g0);
             LAUNCHCHK("k_union_labels");
             HIPCHK(hipStreamSynchronize(c->stream));
-            if (stats) accumulate_stats(acc, st);
-            g0 = g1;
+            if (acc) accumulate_stats(*acc, st);
+        };
+        scc_stats_t acc;
+        memset(&acc, 0, sizeof acc);
+        const int nw = (int)std::min<size_t>((size_t)nstreams, groups.size());
+        if (nw <= 1) {
+            // the workers' buffers of earlier concurrent calls go first
+            for (scc_ctx *w : c->workers) scc_destroy(w);
+            c->workers.clear();
+            for (auto &gr : groups) run_union(c, gr.first, gr.second, stats ? &acc : nullptr);
+        } else {
+            // so do this context's own per-graph buffers and any workers
+            // beyond this call's count: each union's state lives in one place
+            HIPCHK(hipStreamSynchronize(c->stream));
+            release_work_buffers(c);
+            while ((int)c->workers.size() > nw) {
+                scc_destroy(c->workers.back());
+                c->workers.pop_back();
+            }
+            // a different split sizes every union differently: buffers sized
+            // for the old unions go before the new ones are allocated
+            if ((int)c->workers.size() != nw || c->worker_groups != groups.size()) {
+                for (scc_ctx *w : c->workers) {
+                    HIPCHK(hipStreamSynchronize(w->stream));
+                    release_work_buffers(w);
+                }
+                c->worker_groups = groups.size();
+            }
+            // worker contexts, each with its own stream and buffers; they
+            // start once the bases are on the device (the inputs were written
+            // on the calling context's stream before this call)
+            while ((int)c->workers.size() < nw) {
+                scc_ctx_t *w = nullptr;
+                const scc_status cs = scc_create(&w, c->device, nullptr);
+                if (cs != SCC_OK) {
+                    set_err(c, "creating a union worker context failed (%d)", (int)cs);
+                    throw Fail{cs};
+                }
+                c->workers.push_back(w);
+            }
+            std::vector<float> pw;
+            if (c->policy.loaded) {
+                pw.resize(kPolicyFloats);
+                HIPCHK(hipMemcpyAsync(pw.data(), c->policy.w, sizeof(float) * kPolicyFloats, hipMemcpyDeviceToHost,
+                                      c->stream));
+            }
+            HIPCHK(hipStreamSynchronize(c->stream));
+            for (int w = 0; w < nw; w++) {
+                scc_ctx *wc = c->workers[w];
+                if (c->policy.loaded) {
+                    if (policy_load(wc->policy, pw.data(), kPolicyFloats, wc->stream) != 0) {
+                        set_err(c, "policy upload to a union worker failed");
+                        throw Fail{SCC_EHIP};
+                    }
+                } else {
+                    policy_release(wc->policy);
+                }
+            }
+            std::vector<scc_status> rc(nw, SCC_OK);
+            std::vector<std::string> msg(nw);
+            std::vector<scc_stats_t> wacc(nw);
+            for (auto &a : wacc) memset(&a, 0, sizeof a);
+            std::vector<std::thread> th;
+            for (int w = 0; w < nw; w++)
+                th.emplace_back([&, w] {
+                    scc_ctx *wc = c->workers[w];
+                    rc[w] = guard(wc, [&] {
+                        const hipError_t e = hipSetDevice(wc->device);
+                        if (e != hipSuccess) {
+                            set_err(wc, "hipSetDevice failed: %s", hipGetErrorString(e));
+                            throw Fail{SCC_EHIP};
+                        }
+                        for (size_t i = (size_t)w; i < groups.size(); i += (size_t)nw)
+                            run_union(wc, groups[i].first, groups[i].second, stats ? &wacc[w] : nullptr);
+                    });
+                    if (rc[w] != SCC_OK) msg[w] = wc->err;
+                });
+            for (auto &t : th) t.join();
+            for (int w = 0; w < nw; w++)
+                if (rc[w] != SCC_OK) {
+                    set_err(c, "union worker %d: %s", w, msg[w].c_str());
+                    throw Fail{rc[w]};
+                }
+            if (stats)
+                for (int w = 0; w < nw; w++) accumulate_stats(acc, wacc[w]);
         }
         if (stats) {
             acc.n = vtx_base[G];

@@ -51,6 +51,11 @@ def test_kernel_names_follow_the_search_mode():
     assert bench.kernel_name(1, "scc", 1) == "hipscc::k_expand<2, 1>"
     assert bench.kernel_name(1, "scc", 0) == "hipscc::k_expand<1, 1>"
     assert bench.kernel_name(4, "scc", 1) == "hipscc::k_expand_heavy<2>"
+    assert bench.kernel_name(1, "scc", 1, True) == "hipscc::k_expand<5, 1>"
+    assert bench.kernel_name(4, "scc", 1, True) == "hipscc::k_expand_heavy<5>"
+    assert bench.kernel_name(1, "scc", 0, True) == "hipscc::k_expand<1, 1>"
+    o = type("O", (), {"first_slot": 1, "packed": -1})()
+    assert bench.packed_used(o, {"n": 100, "trimmed": 40}) and not bench.packed_used(o, {"n": 100, "trimmed": 60})
     assert bench.kernel_name(0, "cc") == "hipscc::k_expand<3, 1>"
     assert bench.kernel_name(6, "cc") == "hipscc::k_cc_union"
     assert bench.kernel_name(1, "le") == "hipscc::k_expand<4, 1>"

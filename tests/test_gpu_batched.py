@@ -38,7 +38,8 @@ def test_batch_split_into_several_unions(gpu):
     # a batch whose arcs exceed the union limit runs as several disjoint
     # unions (the path the full 4096-graph batch takes at 2^31 arcs); here the
     # limit is lowered so that a small batch splits into many unions, one of
-    # them a single graph larger than the limit
+    # them a single graph larger than the limit, run one after another, two
+    # or four at a time (more unions than streams: each worker runs several)
     import torch
     graphs = graphgen.batched(60, seed=4343, lo_exp=2.0, hi_exp=3.6)
     graphs.insert(17, graphgen.torus(250, 260, 0.6, seed=4344))
@@ -47,24 +48,49 @@ def test_batch_split_into_several_unions(gpu):
     limit = max(total // 7, 1000)
     biggest = int(np.max(np.diff(ab)))
     assert biggest > limit and total > 3 * limit
-    # unions as the library forms them: consecutive graphs while under the limit
-    unions, g0 = 0, 0
-    while g0 < len(graphs):
-        g1 = g0 + 1
-        while g1 < len(graphs) and ab[g1 + 1] - ab[g0] < limit:
-            g1 += 1
-        unions += 1
-        g0 = g1
-    assert unions >= 3
-    print("[case] batch split", len(graphs), "graphs", total, "arcs, limit", limit, "->", unions, "unions", flush=True)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
     arrs = (t(oo), t(oa), t(io), t(ia))
-    got, st = gpu.scc_labels_batched(vb, ab, *arrs, options=gpu.default_options(union_arcs_max=limit),
-                                     return_stats=True)
-    got = got.cpu().numpy()
-    for g, gr in enumerate(graphs):
-        assert np.array_equal(got[vb[g]:vb[g + 1]], oracle.scc_graph(gr)), "graph %d" % g
-    assert st["n_scc"] == sum(len(np.unique(oracle.scc_graph(gr))) for gr in graphs)
+    want = [oracle.scc_graph(gr) for gr in graphs]
+    for streams in (1, 2, 4):
+        print("[case] batch split", len(graphs), "graphs", total, "arcs, limit", limit, "streams", streams,
+              flush=True)
+        got, st = gpu.scc_labels_batched(vb, ab, *arrs,
+                                         options=gpu.default_options(union_arcs_max=limit, union_streams=streams),
+                                         return_stats=True)
+        got = got.cpu().numpy()
+        for g in range(len(graphs)):
+            assert np.array_equal(got[vb[g]:vb[g + 1]], want[g]), "graph %d streams %d" % (g, streams)
+        assert st["n_scc"] == sum(len(np.unique(w)) for w in want)
+
+
+def test_concurrent_unions_match_oracle(gpu):
+    # unions on concurrent streams (worker contexts driven by host threads):
+    # every stream count gives the oracle's labels, on repeated calls (the
+    # workers and their buffers are reused), with kernel timing on, and with
+    # the learned policy (its weights copied to the workers)
+    import os
+    import torch
+    graphs = graphgen.batched(160, seed=4646, lo_exp=2.0, hi_exp=3.8)
+    graphs.insert(40, graphgen.torus(200, 180, 0.5, seed=4647))
+    graphs.insert(110, graphgen.grid(150, 220, 0.5, seed=4648))
+    vb, ab, oo, oa, io, ia = graphgen.concat(graphs)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+    arrs = (t(oo), t(oa), t(io), t(ia))
+    want = [oracle.scc_graph(gr) for gr in graphs]
+    gpu.policy_load(np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                         "paper_2303_04934_amd", "policy_weights.npy")))
+    cases = [dict(union_streams=s) for s in (0, 1, 2, 3, 5)]
+    cases += [dict(union_streams=2, timing=0x7f), dict(union_streams=3, policy=1), dict(union_streams=2, first_slot=0)]
+    for kw in cases:
+        for rep in range(2):
+            print("[case] concurrent unions %s rep %d" % (kw, rep), flush=True)
+            got, st = gpu.scc_labels_batched(vb, ab, *arrs, options=gpu.default_options(**kw), return_stats=True)
+            got = got.cpu().numpy()
+            for g in range(len(graphs)):
+                assert np.array_equal(got[vb[g]:vb[g + 1]], want[g]), "graph %d %s" % (g, kw)
+            assert st["n_scc"] == sum(len(np.unique(w)) for w in want)
+            if kw.get("timing"):  # every frontier kernel timed (a bit per kernel)
+                assert st["launches_kernel"][1] > 0 and st["ms_kernel"][1] > 0
 
 
 def test_batch_with_graph_rounds_and_learned_policy(gpu):
