@@ -482,6 +482,8 @@ struct DriveParams {
     double *resize_ms = nullptr;
     uint64_t peak_fdeg = 0;  // out: largest frontier degree sum seen at a host check
     uint32_t table_full = 0; // out: restarts caused by a full reach table
+    bool abandon_on_overflow = false;  // a multi-source overflow abandons the batch instead of restarting
+    bool abandoned = false;  // out: the batch was abandoned (every lane stopped, nothing cleared yet)
 };
 
 // ExtractAll grid: each block walks 256 stripes (16K slots) per step, and the
@@ -759,6 +761,20 @@ void restart_multi(scc_ctx *c, Lane &L, DriveParams &P, bool table_full, bool la
     if (P.resize_ms) *P.resize_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Clears what an abandoned multi-source search left behind: its reach table,
+// its first-source slots, its bag and its round state.
+void abandon_multi(scc_ctx *c, Lane &L, int64_t n) {
+    fill_u64(c, L.T->p, *L.tslots, kEmpty64);
+    if (L.S.first) fill_u32(c, (uint32_t *)L.S.first, (uint64_t)n, 0xffffffffu);
+    if (L.S.rec) {
+        hipLaunchKernelGGL(k_clear_rec_slots, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, (int32_t)n,
+                           L.S.rec);
+        LAUNCHCHK("k_clear_rec_slots");
+    }
+    reset_bag(c, L.id);
+    reset_lane_ctl(c, L.id);
+}
+
 // Runs seeded lanes until every frontier is empty.
 //
 // Single-source lanes switch between sparse and dense rounds (Section 4.2)
@@ -908,11 +924,17 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
                 c->trace.insert(c->trace.end(), row, row + SCC_TRACE_FIELDS);
             }
             // a multi-source search whose reach table or frontier buffers ran
-            // out restarts with the one that ran out doubled
+            // out restarts with the one that ran out larger, or stops the
+            // whole batch when its caller would rather shrink it
             if (L.mode != kSingle && ((rc.err & kErrTable) || lane_full)) {
                 if (P.st) {
                     P.st->rounds_multi += rc.rounds;  // rounds of the abandoned attempt
                     P.st->restart_rounds += rc.rounds;
+                }
+                if (P.abandon_on_overflow) {
+                    P.abandoned = true;
+                    if (P.st) P.st->table_restarts++;
+                    break;
                 }
                 restart_multi(c, L, P, (rc.err & kErrTable) != 0, lane_full);
                 L.fdeg = L.claims = 0;
@@ -966,6 +988,10 @@ void drive(scc_ctx *c, Lane *lanes, int nl, DriveParams &P) {
                 L.policy_primed = false;
                 switched = true;
             }
+        }
+        if (P.abandoned) {
+            for (int i = 0; i < nl; i++) lanes[i].live = false;
+            break;
         }
         if (launched > limit) {
             set_err(c, "internal: search did not finish after %llu rounds", (unsigned long long)launched);
@@ -1315,7 +1341,10 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         // reached few vertices each cost little more than its fixed launches
         // and checks, so the next one grows by kShortGrowth.
         const double g_fast = short_next ? std::max((double)o.beta_fast, kShortGrowth) : (double)o.beta_fast;
-        bsize *= (g_fast > o.beta && fast_next) ? g_fast : (double)o.beta;
+        const bool grew_fast = g_fast > o.beta && fast_next;
+        const double bsize0 = bsize, prev_bsize0 = prev_bsize;
+        const uint64_t pos0 = pos;
+        bsize *= grew_fast ? g_fast : (double)o.beta;
         const uint64_t sz = std::max<uint64_t>((uint64_t)std::ceil(bsize - 1e-9), 1);
         const uint64_t p1 = std::min<uint64_t>((uint64_t)n, pos + sz);
         const uint64_t kmax = std::min<uint64_t>(p1 - pos, (uint64_t)active);
@@ -1427,9 +1456,26 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
         DP.nsub = active;
         DP.peak_fdeg = 0;
         DP.table_full = 0;
+        DP.abandon_on_overflow = grew_fast;
+        DP.abandoned = false;
         c->epoch = epoch;
         drive(c, L, 2, DP);
         if (DP.table_full) floor_boost = std::min(floor_boost * 2.0, 16.0);
+        if (DP.abandoned) {
+            // A batch that grew faster than beta (its predecessors were
+            // cheap) found more pairs than its tables or frontiers hold: its
+            // sources' reach is larger than the cheap batches suggested, and
+            // pairs grow with the batch, so instead of restarting on larger
+            // buffers the searches are dropped and the batch is taken again
+            // from the same position at the size beta growth gives.
+            for (int d = 0; d < 2; d++) abandon_multi(c, L[d], n);
+            phase_end(c, ph);
+            pos = pos0;
+            bsize = bsize0;
+            prev_bsize = prev_bsize0;
+            fast_next = short_next = false;
+            continue;
+        }
         phase_end(c, ph);
         const uint32_t k = c->hctl->sh.k;
         a_out = c->hctl->lane[0].claims + k;
