@@ -125,7 +125,9 @@ typedef struct {
  *                direction) and cheap in pairs (fewer than 4 reached vertices
  *                per source and direction), the next batch grows by
  *                max(beta_fast, 64).  Any growth factor above 1 keeps
- *                Algorithm 1 correct.  Default 8; <= beta turns both off.
+ *                Algorithm 1 correct.  A batch grown this way that overflows
+ *                its reach table or frontier buffers is abandoned and taken
+ *                again at beta growth.  Default 4; <= beta turns both off.
  *   vgc_fill     local search runs in rounds whose frontier has fewer arcs
  *                (entries x average degree) than vgc_fill x the lanes of the
  *                expand grid; a frontier above that keeps the GPU busy on its

@@ -29,8 +29,9 @@ from . import _native
 # candidate (tau, beta, beta_fast, policy) schedules, the defaults first;
 # policy 1 lets the learned per-round policy pick the budget (tau is then its
 # fallback), so the tuner also decides whether the policy is used
-CANDIDATES = [(2048, 2.0, 8.0, 0), (2048, 2.0, 24.0, 0), (4096, 2.0, 8.0, 0), (2048, 3.0, 8.0, 0),
-              (4096, 2.0, 24.0, 0), (1024, 2.0, 16.0, 0), (2048, 2.0, 8.0, 1), (2048, 2.0, 24.0, 1)]
+CANDIDATES = [(2048, 2.0, 4.0, 0), (2048, 2.0, 8.0, 0), (2048, 2.0, 24.0, 0), (4096, 2.0, 8.0, 0),
+              (2048, 3.0, 8.0, 0), (4096, 2.0, 24.0, 0), (1024, 2.0, 16.0, 0), (2048, 2.0, 4.0, 1),
+              (2048, 2.0, 24.0, 1)]
 
 
 def _subset(vb, ab, arrays, idx):

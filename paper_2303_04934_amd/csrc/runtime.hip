@@ -306,7 +306,7 @@ scc_options_t defaults() {
     memset(&o, 0, sizeof o);
     o.tau = 2048;
     o.beta = 2.0f;
-    o.beta_fast = 8.0f;
+    o.beta_fast = 4.0f;
     o.table_floor = 1.2f;
     o.lambda_log2 = 0;
     o.sigma = 50;

@@ -116,6 +116,21 @@ def test_forced_small_table_restarts(gpu):
     assert st["table_restarts"] > 0
 
 
+@pytest.mark.parametrize("first,packed", [(1, -1), (0, 0)])
+def test_fast_grown_batch_is_retaken(gpu, first, packed):
+    # an R-MAT graph of the 4096-graph batch (scale 15, edge factor 8): after
+    # cheap batches the next one grows 64x into the large subproblem left by
+    # the first SCC, and its pairs outgrow the tables; the batch is abandoned
+    # and retaken at beta growth (before, its tables restarted a dozen times
+    # over about 6.9 million claims)
+    g = graphgen.batched_slice(4096, 1004, 3.0, 6.0, 1770, 1771)[0]
+    assert g.n == 32768
+    st = check_labels(gpu, g, gpu.default_options(first_slot=first, packed=packed),
+                      name="%s first=%d packed=%d" % (g.name, first, packed))
+    assert st["table_restarts"] >= 1
+    assert st["claims"] < 20 * g.n
+
+
 def test_empty_graph(gpu):
     import torch
     say("empty graph")
