@@ -87,11 +87,24 @@ def split(vb, ab, sample_arcs: int | None = None, seed: int = 0):
     return idx, rest
 
 
+MARGIN = 0.03  # a candidate must beat the first (the library default) by this fraction on the sample
+
+
+def choose(times, margin=MARGIN):
+    """Index of the schedule to use: the fastest, unless it is not `margin`
+    faster than the first (the default), which then stays."""
+    best = min(range(len(times)), key=lambda i: times[i])
+    return best if times[best] < times[0] * (1.0 - margin) else 0
+
+
 def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = None, repeats: int = 1,
-         candidates=CANDIDATES, base_options=None, verbose: bool = False, seed: int = 0, held_out: bool = True):
+         candidates=CANDIDATES, base_options=None, verbose: bool = False, seed: int = 0, held_out: bool = True,
+         margin: float = MARGIN):
     """Pick (tau, beta, beta_fast, policy) for a batch.  Returns (options, report):
     each candidate's best time on the sample, and (held_out) the chosen and
-    the default schedule's times on the graphs outside the sample."""
+    the default schedule's times on the graphs outside the sample.  The first
+    candidate stays unless another is faster on the sample by `margin`, so
+    that timing noise between near-equal schedules does not pick the schedule."""
     from . import default_options
     vb = np.asarray(vb, np.int64)
     ab = np.asarray(ab, np.int64)
@@ -99,7 +112,6 @@ def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = Non
     idx, rest = split(vb, ab, sample_arcs, seed)
     svb, sab, sarr = _subset(vb, ab, arrays, idx)
     report = []
-    best = None
     for cand in candidates:
         tau, beta, beta_fast = cand[:3]
         policy = cand[3] if len(cand) > 3 else 0
@@ -114,12 +126,11 @@ def tune(vb, ab, out_off, out_adj, in_off, in_adj, sample_arcs: int | None = Non
         if verbose:
             print("[autotune] tau=%d beta=%.1f beta_fast=%.0f policy=%d sample %.2f ms" %
                   (tau, beta, beta_fast, policy, ms), flush=True)
-        if best is None or ms < best[0]:
-            best = (ms, tau, beta, beta_fast, policy)
     del sarr
     o = default_options() if base_options is None else _copy(base_options)
-    if best is not None:
-        o.tau, o.beta, o.beta_fast, o.policy = best[1], best[2], best[3], best[4]
+    if report:
+        b = report[choose([r["sample_ms"] for r in report], margin)]
+        o.tau, o.beta, o.beta_fast, o.policy = b["tau"], b["beta"], b["beta_fast"], b["policy"]
     rep = {"sample_graphs": len(idx), "sample_arcs": int(sab[-1]) if len(idx) else 0,
            "held_out_graphs": len(rest), "candidates": report}
     if held_out and rest:

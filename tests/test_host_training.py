@@ -110,3 +110,12 @@ def test_class_and_mode_labels_train_dense_outputs_on_single_source_rows_only():
     # the margin lowers every setting but the default (class 2, pull allowed)
     sc2 = pt.scores_for(np.zeros(1, np.int32), times, margin=0.03)
     assert sc2[0, pt.DEFAULT_OUTPUT] == sc[0, pt.DEFAULT_OUTPUT] and sc2[0, 0] < sc[0, 0]
+
+
+def test_autotune_choice_keeps_default_within_margin():
+    from paper_2303_04934_amd import autotune
+    assert autotune.choose([100.0, 98.0, 99.0]) == 0            # 2% better: noise, the default stays
+    assert autotune.choose([100.0, 98.0, 96.0]) == 2            # 4% better: taken
+    assert autotune.choose([100.0, 96.9, 96.0]) == 2            # the fastest of those beyond the margin
+    assert autotune.choose([100.0, 120.0], margin=0.0) == 0
+    assert autotune.choose([100.0, 99.0], margin=0.0) == 1
