@@ -349,7 +349,10 @@ def run_batched(args, desc):
                   kernel_name(dom, "scc", opts.first_slot, packed_used(opts, stats[-1])))
     if rf:
         rf["launches_per_step"] = la_k[dom] / args.steps
-        rf["kernel_share_of_step"] = ms_k[dom] / args.steps / (dt * 1e3)
+        # the unions run on concurrent streams, so the kernel's summed launch
+        # time per step can exceed the step's wall time
+        rf["kernel_ms_per_step_summed_over_streams"] = ms_k[dom] / args.steps
+        rf["union_streams_option"] = opts.union_streams  # 0: the library picks (two streams)
         line["roofline"] = rf
     last = stats[-1]
     line["stats"] = {"kernel_ms_warmup_call": {KERNEL_SHORT[i]: probe_ms[i] for i in range(NK)},
