@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
                 ("beta_fast", ctypes.c_float), ("table_floor", ctypes.c_float), ("union_arcs_max", ctypes.c_int32),
                 ("first_slot", ctypes.c_int32), ("vgc_measure", ctypes.c_int32), ("ldd_beta", ctypes.c_float),
                 ("graph_rounds", ctypes.c_int32), ("packed", ctypes.c_int32),
-                ("union_streams", ctypes.c_int32)]
+                ("union_streams", ctypes.c_int32), ("tau_single", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

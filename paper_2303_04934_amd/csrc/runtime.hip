@@ -324,7 +324,14 @@ scc_options_t defaults() {
     o.first_slot = 1;
     o.packed = -1;
     o.union_streams = 0;
+    o.tau_single = 0;
     return o;
+}
+
+int32_t single_tau(const scc_options_t &o) {
+    if (o.tau_single > 0) return o.tau_single;
+    if (o.tau <= 1) return o.tau;
+    return (int32_t)std::min<int64_t>(4 * (int64_t)o.tau, 1 << 30);
 }
 
 // log2 of the hash bag's first chunk for searches of up to `entries` entries
@@ -373,6 +380,10 @@ void check_opts(scc_ctx *c, const scc_options_t &o) {
     if (o.first_slot < 0 || o.first_slot > 1) { set_err(c, "first_slot must be 0 or 1"); throw Fail{SCC_EINVAL}; }
     if (o.vgc_measure < 0 || o.vgc_measure > 1) { set_err(c, "vgc_measure must be 0 or 1"); throw Fail{SCC_EINVAL}; }
     if (o.packed < -1 || o.packed > 1) { set_err(c, "packed must be -1, 0 or 1"); throw Fail{SCC_EINVAL}; }
+    if (o.tau_single < 0) {
+        set_err(c, "tau_single must be >= 0");
+        throw Fail{SCC_EINVAL};
+    }
     if (o.union_streams < 0 || o.union_streams > kMaxUnionStreams) {
         set_err(c, "union_streams must be in [0, %d]", kMaxUnionStreams);
         throw Fail{SCC_EINVAL};
@@ -438,7 +449,8 @@ Search make_search(scc_ctx *c, int id, const scc_options_t &o, int mode) {
     S.cn = &c->dctl->cn;
     S.kind = (mode == kMulti || mode == kMultiFirst || mode == kLe || mode == kMultiRec) ? kKindExpandMulti
                                                                                         : kKindExpandSingle;
-    S.tau = o.tau;
+    // a single-source search gets the longer budget of tau_single
+    S.tau = mode == kSingle ? single_tau(o) : o.tau;
     S.seeds = o.seeds_per_wave;
     S.heavy_deg = 1024;
     S.probe_limit = kProbeLimit;

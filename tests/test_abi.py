@@ -77,6 +77,7 @@ def test_default_options_and_argument_errors_without_gpu():
     assert (o.tau, o.lambda_log2, o.sigma) == (2048, 0, 50)
     assert abs(o.beta - 2.0) < 1e-6
     assert abs(o.beta_fast - 4.0) < 1e-6 and abs(o.table_floor - 1.2) < 1e-6
+    assert o.tau_single == 0 and o.union_streams == 0
     assert lib.scc_default_options(None) == _native.SCC_EINVAL
     # a NULL context is rejected before any device work
     assert lib.scc_labels(None, None, None, None, None) == _native.SCC_EINVAL

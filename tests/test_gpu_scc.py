@@ -166,6 +166,7 @@ def test_config0_full_size(gpu):
     dict(first_slot=1, arcs_per_lane=2), dict(vgc_measure=1), dict(vgc_measure=1, tau=64, first_slot=1),
     dict(packed=1), dict(packed=0), dict(packed=1, table_init=1024, table_floor=0.0), dict(packed=1, tau=1),
     dict(packed=1, arcs_per_lane=4), dict(packed=1, graph_rounds=1),
+    dict(tau_single=1), dict(tau_single=64), dict(tau_single=65536, tau=1),
 ])
 def test_schedule_invariance(gpu, opt):
     g = graphgen.torus(100, 120, 0.55, seed=77)
