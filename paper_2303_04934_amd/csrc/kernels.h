@@ -85,6 +85,7 @@ struct Shared {
     uint32_t first;        // first active permutation position (batch 1)
     uint32_t emit;         // pairs emitted by scc_reach (entries logged by a LE-lists batch)
     uint32_t bad;          // validation flags
+    uint32_t max_deg;      // largest out- or in-degree of the graph (0: not known yet)
     unsigned long long cursor;  // LE-lists: entries in the list log
 };
 
@@ -147,6 +148,13 @@ struct Search {
     uint8_t *dirty;         // first-source slots: granule flags (null: none kept)
     int32_t *owner;         // kLdd: cluster centre of each claimed vertex
     int32_t level;          // kLe: distance of the entries this round expands
+    // kLe: ExtractAll also logs each new frontier entry (pair key, level + 1)
+    // at position emit + its frontier index (null: not logged)
+    uint64_t *lkeys;
+    int32_t *ldist;
+    uint64_t lcap;
+    uint32_t lkbits;
+    Shared *lsh;
     uint64_t tmask;
     uint32_t probe_limit;
     const int32_t *srclab;  // kMulti: label of source j
@@ -196,6 +204,17 @@ __device__ __forceinline__ void block_add_u32(uint32_t *ctr, uint32_t x) {
     }
 }
 
+// Block-wide maximum of per-thread values, one atomic per block.  Every
+// thread of the block must call it.
+__device__ __forceinline__ void block_max_u32(uint32_t *ctr, uint32_t x) {
+    __shared__ uint32_t m;
+    if (threadIdx.x == 0) m = 0;
+    __syncthreads();
+    if (x) atomicMax(&m, x);
+    __syncthreads();
+    if (threadIdx.x == 0 && m) atomicMax(ctr, m);
+}
+
 // Block-wide reservation: wave w of the block asks for cnt slots (the value
 // of lane 0 counts) and gets the first of its own range; one atomic per
 // block.  Every thread of the block must call it.
@@ -243,14 +262,16 @@ __device__ __forceinline__ unsigned long long block_flush_ctr(unsigned long long
 // pre-set; the source's own bit is set when it is seeded.  A wave covers 64
 // consecutive vertices, i.e. two bitmap words.
 __global__ void k_trim(int32_t n, const int32_t *out_off, const int32_t *in_off, int32_t *label, int32_t do_trim,
-                       uint32_t *vis0, uint32_t *vis1, CountStripes *cs) {
-    uint32_t cnt = 0;
+                       uint32_t *vis0, uint32_t *vis1, CountStripes *cs, Shared *sh) {
+    uint32_t cnt = 0, dmax = 0;
     const int lane = lane_id();
     for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = v0 + threadIdx.x;
         bool t = true;  // past the end: blocked
         if (v < n) {
-            t = do_trim && (out_off[v + 1] == out_off[v] || in_off[v + 1] == in_off[v]);
+            const int32_t dout = out_off[v + 1] - out_off[v], din = in_off[v + 1] - in_off[v];
+            dmax = max(dmax, (uint32_t)max(dout, din));
+            t = do_trim && (dout == 0 || din == 0);
             label[v] = t ? ~(int32_t)v : 0;
             cnt += t;
         }
@@ -262,6 +283,15 @@ __global__ void k_trim(int32_t n, const int32_t *out_off, const int32_t *in_off,
         }
     }
     block_add_u32(&cs->s[blockIdx.x % kStripes].trimmed, cnt);
+    block_max_u32(&sh->max_deg, dmax);
+}
+
+// Largest out-degree (one atomic per block), for searches that skip trimming.
+__global__ void k_max_deg(int32_t n, const int32_t *off, Shared *sh) {
+    uint32_t dmax = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        dmax = max(dmax, (uint32_t)(off[v + 1] - off[v]));
+    block_max_u32(&sh->max_deg, dmax);
 }
 
 // ----------------------------------------------------- source selection ----
@@ -1247,6 +1277,9 @@ __device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t
     if (r >= B.nchunks) r = B.nchunks - 1;
     const uint64_t nst = bag_chunk_hi(B, r) >> kStripeLog2;
     unsigned long long fdeg = 0;
+    // the log's first position for this round (the lane's last block moves
+    // emit past the round's entries once every block has read it)
+    const uint64_t lbase = S.lkeys ? (uint64_t)ld_relaxed(&S.lsh->emit) : 0;
     for (uint64_t sb0 = (uint64_t)bid * kBlock; sb0 < nst; sb0 += (uint64_t)nblk * kBlock) {
         const uint64_t sb = sb0 + (uint64_t)wv * kWave;
         const uint64_t st = sb + lane;
@@ -1276,8 +1309,15 @@ __device__ __forceinline__ void extract_round(const Search &S, int par, uint32_t
             const uint64_t oj = (uint64_t)base + (uint64_t)wave_bcast(excl, j);
             if (lane < cj) {
                 const uint64_t v = B.slots[((sb + j) << kStripeLog2) + lane];
-                if (oj + lane < S.fcap) S.F[oj + lane] = v;
-                else atomicOr(&rc->err, kErrCapacity);
+                if (oj + lane < S.fcap) {
+                    S.F[oj + lane] = v;
+                    if (S.lkeys && lbase + oj + lane < S.lcap) {
+                        S.lkeys[lbase + oj + lane] = ((uint64_t)(uint32_t)key_vertex(v) << S.lkbits) | key_source(v);
+                        S.ldist[lbase + oj + lane] = S.level + 1;
+                    }
+                } else {
+                    atomicOr(&rc->err, kErrCapacity);
+                }
                 if (S.off) {  // the bag self-test extracts keys of no graph
                     const int32_t u = key_vertex(v);
                     fdeg += (unsigned long long)(S.off[u + 1] - S.off[u]);
@@ -1316,6 +1356,10 @@ __device__ __forceinline__ void extract_reset(const Search &S, int par) {
     S.rc->fdeg[par] = 0;
     S.rc->heavy_n[par] = 0;
     stripes_fold(S.rc, S.ls, par);
+    if (S.lkeys) {
+        const uint64_t nf = S.rc->nF[par ^ 1];
+        S.lsh->emit += (uint32_t)(nf < S.fcap ? nf : S.fcap);
+    }
 }
 
 // ExtractAll of one or two lanes (split as in k_expand); each lane's frontier

@@ -263,7 +263,12 @@ int64_t count_sum(const scc_ctx *c, uint32_t CountLine::*f) {
 }
 
 // Zeroes the whole control block inside the stream (a fill kernel, no memset).
-void reset_ctl(scc_ctx *c) { fill_u32(c, (uint32_t *)c->dctl, sizeof(DevCtl) / 4, 0u); }
+// (the host mirror's degree maximum is cleared too: until a check copies the
+// new call's value, a stale one would let a launch skip a needed pass)
+void reset_ctl(scc_ctx *c) {
+    fill_u32(c, (uint32_t *)c->dctl, sizeof(DevCtl) / 4, 0u);
+    c->hctl->sh.max_deg = 0;
+}
 void reset_lane_ctl(scc_ctx *c, int id) { fill_u32(c, (uint32_t *)&c->dctl->lane[id], sizeof(RoundCtl) / 4, 0u); }
 
 uint64_t next_pow2(uint64_t x) {
@@ -627,16 +632,25 @@ void launch_sparse(scc_ctx *c, Lane **ls, int nl) {
     HIPCHK(hipLaunchKernel(fn, dim3(eb), dim3(kBlock), args, 0, c->stream));
     timed_end(c, t);
     P.split = hb / 2;
+    // no vertex of the graph has more arcs than the heavy threshold (known
+    // once a host check has seen the degree maximum): no entry can be
+    // deferred, and the edge-parallel pass has nothing to do
+    const uint32_t dmax = c->hctl->sh.max_deg;
+    const bool no_heavy = dmax > 0 && dmax <= (uint32_t)ls[0]->S.heavy_deg &&
+                          (nl < 2 || dmax <= (uint32_t)ls[1]->S.heavy_deg);
     const bool pairs = mode == kMulti || mode == kMultiFirst || mode == kLe || mode == kMultiRec;
-    const int th = timed_begin(c, pairs ? SCC_KERNEL_HEAVY_MULTI : SCC_KERNEL_HEAVY_SINGLE);
-    if (mode == kMultiRec) hipLaunchKernelGGL(k_expand_heavy<kMultiRec>, dim3(hb), dim3(kBlock), 0, c->stream, P);
-    else if (mode == kLe) hipLaunchKernelGGL(k_expand_heavy<kLe>, dim3(hb), dim3(kBlock), 0, c->stream, P);
-    else if (mode == kLdd) hipLaunchKernelGGL(k_expand_heavy<kLdd>, dim3(hb), dim3(kBlock), 0, c->stream, P);
-    else if (mode == kMultiFirst) hipLaunchKernelGGL(k_expand_heavy<kMultiFirst>, dim3(hb), dim3(kBlock), 0, c->stream, P);
-    else if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
-    else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3(hb), dim3(kBlock), 0, c->stream, P);
-    LAUNCHCHK("k_expand_heavy");
-    timed_end(c, th);
+    if (!no_heavy) {
+        const int th = timed_begin(c, pairs ? SCC_KERNEL_HEAVY_MULTI : SCC_KERNEL_HEAVY_SINGLE);
+        if (mode == kMultiRec) hipLaunchKernelGGL(k_expand_heavy<kMultiRec>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+        else if (mode == kLe) hipLaunchKernelGGL(k_expand_heavy<kLe>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+        else if (mode == kLdd) hipLaunchKernelGGL(k_expand_heavy<kLdd>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+        else if (mode == kMultiFirst)
+            hipLaunchKernelGGL(k_expand_heavy<kMultiFirst>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+        else if (mode == kMulti) hipLaunchKernelGGL(k_expand_heavy<kMulti>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+        else hipLaunchKernelGGL(k_expand_heavy<kSingle>, dim3(hb), dim3(kBlock), 0, c->stream, P);
+        LAUNCHCHK("k_expand_heavy");
+        timed_end(c, th);
+    }
     P.split = xb / 2;
     const int tx = timed_begin(c, SCC_KERNEL_EXTRACT);
     hipLaunchKernelGGL(k_bag_extract, dim3(xb), dim3(kBlock), 0, c->stream, P);
@@ -674,11 +688,14 @@ void launch_dense(scc_ctx *c, Lane &L) {
 // lanes and launch arguments comes again (the bag's per-round salt, which
 // only decorrelates stripe choices, repeats with the graph).
 void run_graph_block(scc_ctx *c, Lane **sp, int nsp, int k) {
-    std::vector<uint8_t> key(2 * sizeof(int) + (size_t)nsp * (sizeof(Search) + sizeof(int)));
+    // (the degree maximum decides whether the block holds edge-parallel passes)
+    const uint32_t dmax = c->hctl->sh.max_deg;
+    std::vector<uint8_t> key(2 * sizeof(int) + sizeof(uint32_t) + (size_t)nsp * (sizeof(Search) + sizeof(int)));
     uint8_t *q = key.data();
     memcpy(q, &k, sizeof(int));
     memcpy(q + sizeof(int), &nsp, sizeof(int));
-    q += 2 * sizeof(int);
+    memcpy(q + 2 * sizeof(int), &dmax, sizeof(uint32_t));
+    q += 2 * sizeof(int) + sizeof(uint32_t);
     for (int j = 0; j < nsp; j++) {
         Search s = sp[j]->S;
         s.bag.salt = 0;
@@ -1247,7 +1264,7 @@ void run_scc(scc_ctx *c, const GraphDev &g, int32_t *labels_out, const scc_optio
     phase_begin(c, 0, ph);
     Shared *sh = &c->dctl->sh;
     hipLaunchKernelGGL(k_trim, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g.out_off, g.in_off,
-                       c->label.p, o.trim ? 1 : 0, c->vis[0].p, c->vis[1].p, &c->dctl->cs);
+                       c->label.p, o.trim ? 1 : 0, c->vis[0].p, c->vis[1].p, &c->dctl->cs, sh);
     LAUNCHCHK("k_trim");
     Perm P;
     P.n = (uint32_t)n;
@@ -1915,6 +1932,7 @@ scc_status scc_create(scc_ctx_t **ctx, int device, void *stream) {
         }
         HIPCHK(hipMalloc((void **)&c->dctl, sizeof(DevCtl)));
         HIPCHK(hipHostMalloc((void **)&c->hctl, sizeof(DevCtl), hipHostMallocDefault));
+        memset(c->hctl, 0, sizeof(DevCtl));
         c->scratch = scratch_address(c);
         reset_ctl(c);
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -2403,6 +2421,10 @@ scc_status scc_cc(scc_ctx_t *c, const scc_graph_t *g, int32_t *labels_out, const
             if (c->hctl->sh.bad) { set_err(c, "invalid CSR (offsets or arc targets)"); throw Fail{SCC_EGRAPH}; }
         }
         int32_t *owner = c->srcvert.p, *parent = c->srclab.p;
+        // the degree maximum (the edge-parallel pass is skipped without heavy vertices)
+        hipLaunchKernelGGL(k_max_deg, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g->out_off,
+                           &c->dctl->sh);
+        LAUNCHCHK("k_max_deg");
         // ---- low-diameter decomposition (Algorithm 4, LDD): one search
         // lane, a centre batch added before every round
         phase_begin(c, 1, ph);
@@ -2554,6 +2576,9 @@ scc_status scc_le_lists(scc_ctx_t *c, const scc_graph_t *g, int32_t *order_out, 
         uint32_t pbits = 1;
         while ((1ll << pbits) < (int64_t)n) pbits++;
         Shared *sh = &c->dctl->sh;
+        // the degree maximum (the edge-parallel pass is skipped without heavy vertices)
+        hipLaunchKernelGGL(k_max_deg, dim3(grid_for(c, (uint64_t)n)), dim3(kBlock), 0, c->stream, n, g->out_off, sh);
+        LAUNCHCHK("k_max_deg");
         uint64_t gcap = 4 * (uint64_t)n + 1024;  // the list log: about n H_n entries expected
         ensure(c, c->gk[0], gcap);
         ensure(c, c->gd[0], gcap);
@@ -2600,6 +2625,12 @@ scc_status scc_le_lists(scc_ctx_t *c, const scc_graph_t *g, int32_t *order_out, 
                 L.S.table = c->Tout.p;
                 L.S.tmask = ts - 1;
                 L.S.tau = 0;  // BFS order: no local search
+                // ExtractAll logs every level's new entries (pair key, distance)
+                L.S.lkeys = c->lk[0].p;
+                L.S.ldist = c->ld[0].p;
+                L.S.lcap = lcap;
+                L.S.lkbits = kbits;
+                L.S.lsh = sh;
                 L.avg_deg = std::max(1.0, (double)g->m / (double)n);
                 L.par = 0;
                 SeedArgs SA;
@@ -2623,9 +2654,6 @@ scc_status scc_le_lists(scc_ctx_t *c, const scc_graph_t *g, int32_t *order_out, 
                         L.S.level = level;
                         Lane *one = &L;
                         launch_sparse(c, &one, 1);
-                        hipLaunchKernelGGL(k_le_log, dim3(extract_blocks(c)), dim3(kBlock), 0, c->stream, L.S.F,
-                                           L.S.rc, L.par, L.S.fcap, level + 1, kbits, c->lk[0].p, c->ld[0].p, lcap, sh);
-                        LAUNCHCHK("k_le_log");
                         level++;
                     }
                     sync_ctl(c);

@@ -131,6 +131,23 @@ def test_fast_grown_batch_is_retaken(gpu, first, packed):
     assert st["claims"] < 20 * g.n
 
 
+def test_hub_pass_with_and_without_heavy_vertices(gpu):
+    # the edge-parallel pass over hub lists is skipped once a check has seen
+    # that no vertex has more than 1024 arcs; alternate calls on one context
+    # between graphs with and without such vertices (a stale degree maximum
+    # would drop the hubs' arcs)
+    n = 6000
+    hub = graphgen.from_arcs(n, np.concatenate([np.zeros(n - 1, np.int64), np.arange(1, n), np.arange(1, n - 1)]),
+                             np.concatenate([np.arange(1, n), np.zeros(n - 1, np.int64), np.arange(2, n)]))
+    one_way = graphgen.from_arcs(n, np.concatenate([np.zeros(n - 1, np.int64), np.arange(1, n - 1)]),
+                                 np.concatenate([np.arange(1, n), np.arange(2, n)]))
+    lattice = graphgen.grid(120, 130, 0.5, seed=91)
+    for rep in range(2):
+        for g, name in ((hub, "wheel"), (lattice, "grid"), (one_way, "fan"), (graphgen.rmat(12, 16, seed=92), "rmat")):
+            for opts in (gpu.default_options(), gpu.default_options(tau=1, dense=0), gpu.default_options(graph_rounds=1)):
+                check_labels(gpu, g, opts, name="%s rep %d" % (name, rep))
+
+
 def test_empty_graph(gpu):
     import torch
     say("empty graph")
